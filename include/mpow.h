@@ -1,0 +1,154 @@
+/*
+ * mpow - integer matrix power A^p on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one the paper computes in section 4: the p-th power of
+ * a dense N x N matrix.  The paper's method (section 4.3) reaches A^p with a
+ * number of matrix products logarithmic in p instead of the p-1 chained
+ * products of the naive method (sections 4.1 and 4.2).  This library uses
+ * left-to-right binary exponentiation: for every bit of p below the leading
+ * one it squares the running matrix X <- X.X, and when that bit is set it
+ * multiplies once more by the base, X <- X.A.  That is floor(log2 p) squarings
+ * plus popcount(p)-1 multiplications, G(p) products in total.
+ *
+ * Range.  A^p leaves every floating-point range for the paper's powers (up to
+ * 1024) unless A is scaled.  After each product the running matrix is scaled
+ * by an exact power of two 2^-e, e = floor(log2 ||X||_F), and e is folded into
+ * an integer log2 scale s carried in float64.  Scaling by a power of two is
+ * exact, so it changes no rounding; it only keeps values in range.
+ *
+ * Conventions for every call below:
+ *  - Matrices are float32, row-major, contiguous, n x n (element (i,j) at
+ *    index i*n + j).  Matrix and scale pointers passed to run calls are
+ *    DEVICE pointers on the plan's device, owned by the caller; the library
+ *    never frees or keeps them past the call's completion on the stream.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).  Run
+ *    calls only enqueue work; they never synchronise with the host.
+ *  - Every call returns an mpow_status; nothing throws across this boundary.
+ *    Argument errors are detected on the host before anything is enqueued.
+ *  - A plan is not thread-safe, and one plan must not have two runs in flight
+ *    on different streams at once (they share its workspace).  Use one plan
+ *    per concurrent stream.
+ */
+#ifndef MPOW_H
+#define MPOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mpow_status {
+    MPOW_SUCCESS = 0,
+    MPOW_ERR_INVALID = 1,     /* bad argument (null, n<1, n>max_n, p<0, overlap) */
+    MPOW_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+    MPOW_ERR_NOMEM = 3,       /* device or pinned host allocation failed */
+    MPOW_ERR_DEVICE = 4,      /* a HIP call failed; see mpow_last_device_error */
+    MPOW_ERR_BUDGET = 5       /* request can never fit the memory budget */
+} mpow_status;
+
+/* Arithmetic of the matrix products.  Inputs and outputs are float32 in every
+ * mode.  MPOW_FP32: float32 MFMA products with float32 accumulation. */
+typedef enum mpow_mode {
+    MPOW_FP32 = 0,
+    MPOW_FP16X3 = 1,
+    MPOW_BF16X3 = 2
+} mpow_mode;
+
+/* Plan flags. */
+#define MPOW_FLAG_TIMING 1u /* record a pair of HIP events around every product
+                               kernel launch; read with mpow_plan_timing */
+#define MPOW_FLAG_POISON 2u /* testing: fill the workspace with NaN bytes at
+                               creation instead of zeros, so a read of memory
+                               the run has not written shows in the result */
+
+/* Upper bound on the number of products of one power (p < 2^63 needs <= 124). */
+#define MPOW_MAX_STEPS 126
+
+typedef struct mpow_plan *mpow_plan_t;
+
+/* Static description of a status code.  Never NULL. */
+const char *mpow_status_str(int status);
+
+/* G(p) = floor(log2 p) + popcount(p) - 1 for p >= 2, 0 for p in {0,1},
+ * -1 for p < 0.  Host only; never touches a device. */
+int mpow_gemm_count(int64_t p);
+
+/* Writes the product schedule of p (section 4.3, left-to-right binary
+ * exponentiation) into ops[0..G(p)-1]: 0 = square X <- X.X, 1 = multiply
+ * X <- X.A.  Returns G(p), or -1 if p < 0, ops is NULL while G(p) > 0, or
+ * cap < G(p).  Host only. */
+int mpow_schedule(int64_t p, uint8_t *ops, int cap);
+
+/* Device bytes a plan for (max_n, max_batch, mode) allocates; 0 for invalid
+ * arguments.  Host only. */
+size_t mpow_workspace_bytes(int max_n, int max_batch, int mode);
+
+/* Creates a plan on HIP device `device` for matrices up to max_n x max_n and
+ * batches of up to max_batch matrices (0: no batched calls).  All device
+ * workspace is allocated here, never on the run path.  `mode` is an
+ * mpow_mode.  On success *plan owns the workspace until mpow_plan_destroy.
+ * Errors: INVALID (plan NULL, max_n < 1, max_batch < 0, unknown mode/flags),
+ * UNSUPPORTED (mode not built), DEVICE (no such device / HIP failure),
+ * NOMEM (allocation failed; nothing is leaked). */
+mpow_status mpow_plan_create(mpow_plan_t *plan, int device, int max_n, int max_batch,
+                             int mode, uint32_t flags);
+
+/* Frees the plan's workspace after waiting for the device to finish work
+ * that uses it.  NULL is accepted and ignored. */
+mpow_status mpow_plan_destroy(mpow_plan_t plan);
+
+/* A^p (sections 4.3 and 4.1 for the definition).
+ *   A          device, n*n float32, read only.
+ *   n          1 <= n <= the plan's max_n.
+ *   p          p >= 0.  p = 0 gives the identity (also for singular A),
+ *              p = 1 gives A.
+ *   out        device, n*n float32, written.  It may be the same pointer as
+ *              A; any other overlap with A is INVALID.
+ *   log2_scale NULL: out = A^p rounded to float32 (entries beyond float32
+ *              range become +-inf or 0).  Non-NULL (device, one double):
+ *              out = M and *log2_scale = s with A^p = M * 2^s and
+ *              ||M||_F in [1, 2); s is an integer held in a double.  A zero
+ *              result (zero A, or a power of a nilpotent A that vanishes)
+ *              gives M = 0 and s = 0.
+ * NaN or Inf entries propagate into the result (status is still SUCCESS).
+ * Errors: INVALID (arguments), DEVICE (launch failure). */
+mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
+                     double *log2_scale, void *stream);
+
+/* `count` independent powers in one call: matrix i is A[i] (device pointer,
+ * n[i] x n[i]) raised to p[i] into out[i], with log2_scale[i] as in mpow_run
+ * (log2_scale itself may be NULL: no scales for any matrix).  A, n, p and out
+ * are HOST arrays of length count.  Per-matrix semantics equal mpow_run's.
+ * Errors: INVALID (count < 0 or > max_batch, any per-matrix argument invalid,
+ * n[i] > 256), DEVICE. */
+mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A, const int *n,
+                             const int64_t *p, float *const *out, double *log2_scale,
+                             void *stream);
+
+/* The last hipError_t value a call on this plan saw (0 if none). */
+int mpow_last_device_error(mpow_plan_t plan);
+
+/* Kernel identifiers for timing queries. */
+enum {
+    MPOW_KERNEL_GEMM_F32_128 = 0, /* float32 product, 128x128 tiles */
+    MPOW_KERNEL_GEMM_F32_64 = 1,  /* float32 product, 64x64 tiles */
+    MPOW_KERNEL_GEMM_F32_32 = 2,  /* float32 product, 32x32 tiles */
+    MPOW_KERNEL_COUNT = 8
+};
+
+/* Timing of product launches recorded under MPOW_FLAG_TIMING since the last
+ * reset: number of launches, summed event-measured milliseconds and summed
+ * algorithmic flops (2 n^3 per product).  Waits for the recorded events.
+ * The name written to *name (may be NULL) is the kernel's symbol name.
+ * Errors: INVALID (plan NULL, flag not set, bad kernel id), DEVICE. */
+mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, double *total_ms,
+                             double *total_flop, const char **name);
+mpow_status mpow_plan_timing_reset(mpow_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPOW_H */

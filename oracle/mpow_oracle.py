@@ -269,10 +269,11 @@ def perturbed(A: np.ndarray, signs: np.ndarray) -> np.ndarray:
     return A * (1.0 + signs * 2.0 ** -24)
 
 
-def floor_estimate(A: np.ndarray, p: int, signs: np.ndarray) -> float:
+def floor_estimate(A: np.ndarray, p: int, signs: np.ndarray, ref=None) -> float:
     """Sensitivity of A^p to float32-sized input noise: the oracle's relative
-    change when each entry of A moves by a random relative +-2^-24."""
-    M, s = mpow_binary(A, p)
+    change when each entry of A moves by a random relative +-2^-24.
+    `ref` may pass the already computed (M, s) of A^p."""
+    M, s = mpow_binary(A, p) if ref is None else ref
     Mp, sp = mpow_binary(perturbed(A, signs), p)
     return rel_err(Mp, sp, M, s)
 

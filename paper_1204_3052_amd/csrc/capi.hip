@@ -1,0 +1,310 @@
+// C ABI of the library: argument checks, the product schedule of p, plan and
+// workspace ownership, and the enqueueing of one power.
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "mpow_internal.h"
+
+using namespace mpow;
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+mpow_status device_error(mpow_plan *plan, hipError_t e) {
+    if (plan) plan->last_error = (int)e;
+    return MPOW_ERR_DEVICE;
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace sizes, in bytes, for a plan of max_n.
+struct Sizes {
+    size_t buf, part, partA, escale, total;
+};
+
+bool sizes_for(int max_n, Sizes *z) {
+    if (max_n < 1) return false;
+    const size_t n = (size_t)max_n;
+    const size_t t32 = (n + 31) / 32;
+    z->buf = round_up(n * n * sizeof(float), 256);
+    z->part = round_up(t32 * t32 * sizeof(double), 256);
+    z->partA = round_up(512 * sizeof(double), 256);
+    z->escale = round_up((MPOW_MAX_STEPS + 2) * sizeof(int), 256);
+    z->total = 2 * z->buf + 2 * z->part + z->partA + z->escale;
+    return true;
+}
+
+bool ranges_overlap(const void *a, const void *b, size_t bytes) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+int popcount64(uint64_t v) { return __builtin_popcountll(v); }
+
+hipEvent_t take_event(mpow_plan *plan) {
+    if (!plan->free_events.empty()) {
+        hipEvent_t e = plan->free_events.back();
+        plan->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpow_status_str(int status) {
+    switch (status) {
+        case MPOW_SUCCESS: return "success";
+        case MPOW_ERR_INVALID: return "invalid argument";
+        case MPOW_ERR_UNSUPPORTED: return "unsupported";
+        case MPOW_ERR_NOMEM: return "out of memory";
+        case MPOW_ERR_DEVICE: return "device error";
+        case MPOW_ERR_BUDGET: return "exceeds memory budget";
+        default: return "unknown status";
+    }
+}
+
+int mpow_gemm_count(int64_t p) {
+    if (p < 0) return -1;
+    if (p < 2) return 0;
+    const int top = 63 - __builtin_clzll((unsigned long long)p);
+    return top + popcount64((uint64_t)p) - 1;
+}
+
+int mpow_schedule(int64_t p, uint8_t *ops, int cap) {
+    const int g = mpow_gemm_count(p);
+    if (g < 0) return -1;
+    if (g == 0) return 0;
+    if (!ops || cap < g) return -1;
+    const int top = 63 - __builtin_clzll((unsigned long long)p);
+    int k = 0;
+    for (int bit = top - 1; bit >= 0; --bit) {
+        ops[k++] = 0;
+        if ((p >> bit) & 1) ops[k++] = 1;
+    }
+    return k;
+}
+
+size_t mpow_workspace_bytes(int max_n, int max_batch, int mode) {
+    Sizes z;
+    if (max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 || !sizes_for(max_n, &z)) return 0;
+    return z.total;
+}
+
+mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int max_batch,
+                             int mode, uint32_t flags) {
+    if (!out_plan) return MPOW_ERR_INVALID;
+    *out_plan = nullptr;
+    if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 ||
+        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON)) != 0)
+        return MPOW_ERR_INVALID;
+    if (mode != MPOW_FP32) return MPOW_ERR_UNSUPPORTED;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return MPOW_ERR_DEVICE;
+    Sizes z;
+    sizes_for(max_n, &z);
+
+    mpow_plan *plan = new (std::nothrow) mpow_plan();
+    if (!plan) return MPOW_ERR_NOMEM;
+    plan->device = device;
+    plan->max_n = max_n;
+    plan->max_batch = max_batch;
+    plan->mode = mode;
+    plan->flags = flags;
+
+    DeviceGuard guard(device);
+    if (!guard.ok) {
+        delete plan;
+        return MPOW_ERR_DEVICE;
+    }
+    char *base = nullptr;
+    hipError_t e = hipMalloc((void **)&base, z.total);
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        delete plan;
+        return MPOW_ERR_NOMEM;
+    }
+    e = hipMemset(base, (flags & MPOW_FLAG_POISON) ? 0xFF : 0, z.total);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        delete plan;
+        return MPOW_ERR_DEVICE;
+    }
+    char *q = base;
+    plan->ws.buf[0] = (float *)q; q += z.buf;
+    plan->ws.buf[1] = (float *)q; q += z.buf;
+    plan->ws.part[0] = (double *)q; q += z.part;
+    plan->ws.part[1] = (double *)q; q += z.part;
+    plan->ws.partA = (double *)q; q += z.partA;
+    plan->ws.escale = (int *)q; q += z.escale;
+    plan->ws.part_cap = z.part / sizeof(double);
+    plan->ws.partA_cap = z.partA / sizeof(double);
+    *out_plan = plan;
+    return MPOW_SUCCESS;
+}
+
+mpow_status mpow_plan_destroy(mpow_plan_t plan) {
+    if (!plan) return MPOW_SUCCESS;
+    DeviceGuard guard(plan->device);
+    (void)hipDeviceSynchronize();
+    for (auto &r : plan->pending) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : plan->free_events) (void)hipEventDestroy(e);
+    (void)hipFree(plan->ws.buf[0]);
+    delete plan;
+    return MPOW_SUCCESS;
+}
+
+int mpow_last_device_error(mpow_plan_t plan) { return plan ? plan->last_error : 0; }
+
+mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
+                     double *log2_scale, void *stream) {
+    if (!plan || !A || !out || n < 1 || p < 0) return MPOW_ERR_INVALID;
+    if (n > plan->max_n) return MPOW_ERR_INVALID;
+    const size_t bytes = (size_t)n * (size_t)n * sizeof(float);
+    if ((const void *)A != (const void *)out && ranges_overlap(A, out, bytes))
+        return MPOW_ERR_INVALID;
+    if (((uintptr_t)A & 3) || ((uintptr_t)out & 3) || ((uintptr_t)log2_scale & 7))
+        return MPOW_ERR_INVALID;
+    if (log2_scale && (ranges_overlap(log2_scale, A, bytes) || ranges_overlap(log2_scale, out, bytes)))
+        return MPOW_ERR_INVALID;
+
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return device_error(plan, hipErrorInvalidDevice);
+    Workspace &ws = plan->ws;
+    hipError_t e;
+
+    if (p == 0) {
+        e = launch_identity(out, n, log2_scale, s);
+        return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
+    }
+
+    const int nbA = norm_blocks(n);
+    e = launch_sumsq(A, n, ws.partA, nbA, s);
+    if (e != hipSuccess) return device_error(plan, e);
+
+    uint8_t ops[MPOW_MAX_STEPS];
+    const int G = mpow_schedule(p, ops, MPOW_MAX_STEPS);
+    const int kernel = gemm_pick(n);
+    const int tiles = gemm_tiles(kernel, n);
+    const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    const bool timing = (plan->flags & MPOW_FLAG_TIMING) != 0;
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+
+    const float *X = A;
+    const double *partX = ws.partA;
+    int nPartX = nbA;
+    for (int k = 1; k <= G; ++k) {
+        GemmLaunch g;
+        g.X = X;
+        g.partX = partX;
+        g.nPartX = nPartX;
+        if (ops[k - 1] == 0) {
+            g.Y = X;
+            g.partY = partX;
+            g.nPartY = nPartX;
+        } else {
+            g.Y = A;
+            g.partY = ws.partA;
+            g.nPartY = nbA;
+        }
+        g.C = ws.buf[k & 1];
+        g.partC = ws.part[k & 1];
+        g.eSlot = ws.escale + (k - 1);
+        g.n = n;
+        TimingRecord rec{};
+        if (timing) {
+            rec.kernel = kernel;
+            rec.flop = flop;
+            rec.start = take_event(plan);
+            rec.stop = take_event(plan);
+            if (!rec.start || !rec.stop) return device_error(plan, hipErrorOutOfMemory);
+            e = hipEventRecord(rec.start, s);
+            if (e != hipSuccess) return device_error(plan, e);
+        }
+        e = gemm_launch(kernel, g, vec4, s);
+        if (e != hipSuccess) return device_error(plan, e);
+        if (timing) {
+            e = hipEventRecord(rec.stop, s);
+            if (e != hipSuccess) return device_error(plan, e);
+            plan->pending.push_back(rec);
+        }
+        X = g.C;
+        partX = g.partC;
+        nPartX = tiles;
+    }
+
+    e = launch_finish(X, n, partX, nPartX, ws.escale, p, G, out, log2_scale, s);
+    return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
+}
+
+mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A, const int *n,
+                             const int64_t *p, float *const *out, double *log2_scale,
+                             void *stream) {
+    if (!plan || count < 0 || count > plan->max_batch) return MPOW_ERR_INVALID;
+    if (count > 0 && (!A || !n || !p || !out)) return MPOW_ERR_INVALID;
+    (void)log2_scale;
+    (void)stream;
+    return MPOW_ERR_UNSUPPORTED;
+}
+
+mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, double *total_ms,
+                             double *total_flop, const char **name) {
+    if (!plan || !(plan->flags & MPOW_FLAG_TIMING) || kernel < 0 || kernel >= MPOW_KERNEL_COUNT)
+        return MPOW_ERR_INVALID;
+    DeviceGuard guard(plan->device);
+    for (auto &r : plan->pending) {
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return device_error(plan, e);
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess) return device_error(plan, e);
+        plan->launches[r.kernel] += 1;
+        plan->ms[r.kernel] += ms;
+        plan->flop[r.kernel] += r.flop;
+        plan->free_events.push_back(r.start);
+        plan->free_events.push_back(r.stop);
+    }
+    plan->pending.clear();
+    if (launches) *launches = plan->launches[kernel];
+    if (total_ms) *total_ms = plan->ms[kernel];
+    if (total_flop) *total_flop = plan->flop[kernel];
+    if (name) *name = gemm_name(kernel);
+    return MPOW_SUCCESS;
+}
+
+mpow_status mpow_plan_timing_reset(mpow_plan_t plan) {
+    if (!plan) return MPOW_ERR_INVALID;
+    int64_t l;
+    double m, f;
+    mpow_status st = MPOW_SUCCESS;
+    if (plan->flags & MPOW_FLAG_TIMING) st = mpow_plan_timing(plan, 0, &l, &m, &f, nullptr);
+    for (int k = 0; k < MPOW_KERNEL_COUNT; ++k) {
+        plan->launches[k] = 0;
+        plan->ms[k] = 0.0;
+        plan->flop[k] = 0.0;
+    }
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mpow.h"
+
+namespace mpow {
+
+// Workspace layout of one plan (all device memory, allocated at plan creation).
+//  buf[0], buf[1]  ping-pong running matrices, max_n^2 floats each
+//  part[0], part[1] per-tile partial sums of squares of buf[0] / buf[1]
+//  partA            per-block partial sums of squares of the input A
+//  escale           escale[k] = floor(log2 ||C_k||_F) of the k-th product's
+//                   output (C_0 = A), written by the kernel that consumes C_k
+struct Workspace {
+    float *buf[2] = {nullptr, nullptr};
+    double *part[2] = {nullptr, nullptr};
+    double *partA = nullptr;
+    int *escale = nullptr;
+    size_t part_cap = 0;   // doubles in each part[] array
+    size_t partA_cap = 0;  // doubles in partA
+};
+
+// How one product kernel is launched.
+struct GemmLaunch {
+    const float *X;          // left operand (scaled by 2^-eX on load)
+    const double *partX;     // partial sums of squares of X
+    int nPartX;
+    const float *Y;          // right operand (scaled by 2^-eY on load)
+    const double *partY;
+    int nPartY;
+    float *C;                // output, n x n
+    double *partC;           // output partials, one per tile
+    int *eSlot;              // where block 0 records eX (may be null)
+    int n;
+};
+
+// Product kernel variants (index = MPOW_KERNEL_* id).
+int gemm_pick(int n);                       // kernel id used for size n
+int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
+const char *gemm_name(int kernel);
+hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s);
+
+// Scale and bookkeeping kernels.
+int norm_blocks(int n);
+hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s);
+hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s);
+hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
+                         const int *escale, int64_t p, int steps, float *out,
+                         double *log2_scale, hipStream_t s);
+
+}  // namespace mpow
+
+struct TimingRecord {
+    int kernel;
+    double flop;
+    hipEvent_t start, stop;
+};
+
+struct mpow_plan {
+    int device = 0;
+    int max_n = 0;
+    int max_batch = 0;
+    int mode = 0;
+    uint32_t flags = 0;
+    int last_error = 0;
+    mpow::Workspace ws;
+    // timing (MPOW_FLAG_TIMING)
+    std::vector<hipEvent_t> free_events;
+    std::vector<TimingRecord> pending;
+    int64_t launches[MPOW_KERNEL_COUNT] = {};
+    double ms[MPOW_KERNEL_COUNT] = {};
+    double flop[MPOW_KERNEL_COUNT] = {};
+};

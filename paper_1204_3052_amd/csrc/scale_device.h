@@ -1,0 +1,67 @@
+// Device helpers for the power-of-two scaling of the running matrix.
+//
+// After every product the running matrix X is rescaled by 2^-e with
+// e = floor(log2 ||X||_F).  The Frobenius norm comes from per-tile partial
+// sums of squares (float64) that the producing kernel writes; every consumer
+// block reduces the same partial array in the same fixed order, so all blocks
+// of a launch derive the same e, and repeated runs give identical bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mpow {
+
+// floor(log2 sqrt(S)) for a sum of squares S; 0 when S is 0, NaN or Inf
+// (no scaling is applied then).  With S = m * 2^q, m in [0.5, 1):
+// floor(log2 S) = q - 1 and floor(log2 sqrt S) = floor((q - 1) / 2).
+__device__ __forceinline__ int exponent_of_sumsq(double S) {
+    if (!(S > 0.0) || !isfinite(S)) return 0;
+    int q;
+    (void)frexp(S, &q);
+    const int t = q - 1;
+    return t >= 0 ? t / 2 : -((1 - t) / 2);
+}
+
+// The multiplier 2^-e as two float factors, each a normal float for any e a
+// float32 matrix can produce (|e| < 160), so x * f.lo * f.hi is exact
+// whenever the result is a normal float.
+struct PowScale {
+    float a, b;
+};
+__device__ __forceinline__ PowScale pow2_neg(int e) {
+    const int h = e / 2;
+    PowScale f;
+    f.a = ldexpf(1.0f, -h);
+    f.b = ldexpf(1.0f, -(e - h));
+    return f;
+}
+
+// Sum of `count` float64 partials in a fixed order, returned to every thread
+// of the block.  `red` is LDS scratch of NT doubles.  Contains barriers: all
+// threads of the block must call it.
+template <int NT>
+__device__ __forceinline__ double block_sum_partials(const double *__restrict__ part, int count,
+                                                     double *red) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += NT) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double S = red[0];
+    __syncthreads();
+    return S;
+}
+
+// Fixed-order reduction of one double per lane across a 64-lane wave; the
+// result is valid in lane 0.
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+}  // namespace mpow

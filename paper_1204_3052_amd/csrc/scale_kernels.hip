@@ -1,0 +1,142 @@
+// Memory-bound kernels around the products: the input's sum of squares, the
+// identity for p = 0, and the final rescale that turns the last running
+// matrix into the caller's output (the only float64 arithmetic on the path).
+#include "mpow_internal.h"
+#include "scale_device.h"
+
+namespace mpow {
+
+namespace {
+
+constexpr int kNT = 256;
+
+// Partial sums of squares of A (float64), block b covering one contiguous
+// chunk of the n*n elements in a fixed order.
+__global__ __launch_bounds__(kNT) void sumsq_kernel(const float *__restrict__ A, int64_t total,
+                                                    int64_t chunk, double *__restrict__ part) {
+    __shared__ double red[kNT];
+    const int64_t begin = (int64_t)blockIdx.x * chunk;
+    const int64_t end = begin + chunk < total ? begin + chunk : total;
+    double acc = 0.0;
+    for (int64_t i = begin + threadIdx.x; i < end; i += kNT) {
+        const double v = (double)A[i];
+        acc += v * v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int s = kNT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kNT) void identity_kernel(float *__restrict__ out, int n,
+                                                       double *__restrict__ log2_scale) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kNT) {
+        const int64_t r = i / n, c = i - r * n;
+        out[i] = (r == c) ? 1.0f : 0.0f;
+    }
+    if (log2_scale && blockIdx.x == 0 && threadIdx.x == 0) *log2_scale = 0.0;
+}
+
+// Final step.  C holds the last product C_G; its true value is C_G * 2^(s_G),
+// where s_G follows from the recorded exponents:
+//   square   : s_k = 2 (s_{k-1} + e_{k-1})
+//   multiply : s_k = s_{k-1} + e_{k-1} + e_0
+// (e_k = floor(log2 ||C_k||_F), C_0 = A, s_0 = 0).
+// log2_scale == NULL: out = C_G * 2^(s_G) rounded to float32 via float64.
+// Otherwise        : out = C_G * 2^(-e_G) and *log2_scale = s_G + e_G, or
+//                    0 when C_G is exactly zero.
+__global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
+                                                     const double *__restrict__ partC, int nPartC,
+                                                     const int *__restrict__ escale, int64_t p,
+                                                     float *out,
+                                                     double *__restrict__ log2_scale) {
+    // C and out may be the same buffer (p = 1 with out == A): every element is
+    // read and then written by the same thread.
+    __shared__ double red[kNT];
+    __shared__ double sh_sG;
+    __shared__ int sh_eG;
+    __shared__ int sh_zero;
+    const double S = block_sum_partials<kNT>(partC, nPartC, red);
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        if (p >= 2) {
+            const int e0 = escale[0];
+            int k = 1;
+            const int top = 63 - __clzll((unsigned long long)p);
+            for (int bit = top - 1; bit >= 0; --bit) {
+                s = 2.0 * (s + (double)escale[k - 1]);
+                ++k;
+                if ((p >> bit) & 1) {
+                    s = s + (double)escale[k - 1] + (double)e0;
+                    ++k;
+                }
+            }
+        }
+        sh_sG = s;
+        sh_eG = exponent_of_sumsq(S);
+        sh_zero = (S == 0.0);
+        if (log2_scale && blockIdx.x == 0) *log2_scale = sh_zero ? 0.0 : s + (double)sh_eG;
+    }
+    __syncthreads();
+    const int64_t total = (int64_t)n * n;
+    if (log2_scale) {
+        const PowScale f = pow2_neg(sh_eG);
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total;
+             i += (int64_t)gridDim.x * kNT)
+            out[i] = C[i] * f.a * f.b;
+    } else {
+        double sG = sh_sG;
+        sG = sG > 4000.0 ? 4000.0 : (sG < -4000.0 ? -4000.0 : sG);
+        const int si = (int)sG;
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total;
+             i += (int64_t)gridDim.x * kNT)
+            out[i] = (float)ldexp((double)C[i], si);
+    }
+}
+
+int grid_for(int64_t total, int cap) {
+    int64_t g = (total + kNT * 4 - 1) / (kNT * 4);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+int norm_blocks(int n) {
+    const int64_t total = (int64_t)n * n;
+    int64_t b = (total + 8191) / 8192;
+    if (b < 1) b = 1;
+    if (b > 512) b = 512;
+    return (int)b;
+}
+
+hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s) {
+    const int64_t total = (int64_t)n * n;
+    const int64_t chunk = (total + blocks - 1) / blocks;
+    hipLaunchKernelGGL(sumsq_kernel, dim3(blocks), dim3(kNT), 0, s, A, total, chunk, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s) {
+    hipLaunchKernelGGL(identity_kernel, dim3(grid_for((int64_t)n * n, 1024)), dim3(kNT), 0, s,
+                       out, n, log2_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
+                         const int *escale, int64_t p, int steps, float *out,
+                         double *log2_scale, hipStream_t s) {
+    (void)steps;
+    hipLaunchKernelGGL(finish_kernel, dim3(grid_for((int64_t)n * n, 512)), dim3(kNT), 0, s, C, n,
+                       partC, nPartC, escale, p, out, log2_scale);
+    return hipGetLastError();
+}
+
+}  // namespace mpow

@@ -1,0 +1,221 @@
+"""Python binding of libmpow (ctypes).
+
+Argument marshalling only: every function below forwards to the C entry point
+of the same name declared in include/mpow.h, and every step of the power runs
+in the library's HIP kernels.  PyTorch is used only to hand over device memory
+(``tensor.data_ptr()``) and streams (``torch.cuda.current_stream()``).  If the
+library has not been built, the first call raises - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpow.so")
+
+MPOW_SUCCESS = 0
+MPOW_ERR_INVALID = 1
+MPOW_ERR_UNSUPPORTED = 2
+MPOW_ERR_NOMEM = 3
+MPOW_ERR_DEVICE = 4
+MPOW_ERR_BUDGET = 5
+
+MPOW_FP32 = 0
+MPOW_FP16X3 = 1
+MPOW_BF16X3 = 2
+
+MPOW_FLAG_TIMING = 1
+MPOW_FLAG_POISON = 2
+MPOW_MAX_STEPS = 126
+
+MPOW_KERNEL_GEMM_F32_128 = 0
+MPOW_KERNEL_GEMM_F32_64 = 1
+MPOW_KERNEL_GEMM_F32_32 = 2
+MPOW_KERNEL_COUNT = 8
+
+# every symbol include/mpow.h declares
+EXPORTS = (
+    "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_workspace_bytes",
+    "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_batched",
+    "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
+)
+
+_lib = None
+
+
+class MpowError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {mpow_status_str(status)} (status {status})")
+        self.status = status
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1204_3052_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    P = c.c_void_p
+    sig = {
+        "mpow_status_str": (c.c_char_p, [c.c_int]),
+        "mpow_gemm_count": (c.c_int, [c.c_int64]),
+        "mpow_schedule": (c.c_int, [c.c_int64, P, c.c_int]),
+        "mpow_workspace_bytes": (c.c_size_t, [c.c_int, c.c_int, c.c_int]),
+        "mpow_plan_create": (c.c_int, [c.POINTER(P), c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint32]),
+        "mpow_plan_destroy": (c.c_int, [P]),
+        "mpow_run": (c.c_int, [P, P, c.c_int, c.c_int64, P, P, P]),
+        "mpow_run_batched": (c.c_int, [P, c.c_int, P, P, P, P, P, P]),
+        "mpow_last_device_error": (c.c_int, [P]),
+        "mpow_plan_timing": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_double),
+                                       c.POINTER(c.c_double), c.POINTER(c.c_char_p)]),
+        "mpow_plan_timing_reset": (c.c_int, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != MPOW_SUCCESS:
+        raise MpowError(status, what)
+
+
+# ---------------------------------------------------------------- raw ABI
+
+def mpow_status_str(status: int) -> str:
+    return _load().mpow_status_str(int(status)).decode()
+
+
+def mpow_gemm_count(p: int) -> int:
+    return int(_load().mpow_gemm_count(int(p)))
+
+
+def mpow_schedule(p: int) -> list:
+    ops = (ctypes.c_uint8 * MPOW_MAX_STEPS)()
+    g = _load().mpow_schedule(int(p), ctypes.cast(ops, ctypes.c_void_p), MPOW_MAX_STEPS)
+    if g < 0:
+        raise MpowError(MPOW_ERR_INVALID, "mpow_schedule")
+    return [int(ops[i]) for i in range(g)]
+
+
+def mpow_workspace_bytes(max_n: int, max_batch: int = 0, mode: int = MPOW_FP32) -> int:
+    return int(_load().mpow_workspace_bytes(int(max_n), int(max_batch), int(mode)))
+
+
+def mpow_plan_create(device: int, max_n: int, max_batch: int = 0, mode: int = MPOW_FP32,
+                     flags: int = 0) -> int:
+    h = ctypes.c_void_p()
+    st = _load().mpow_plan_create(ctypes.byref(h), int(device), int(max_n), int(max_batch),
+                                  int(mode), int(flags))
+    _check(st, "mpow_plan_create")
+    return h.value
+
+
+def mpow_plan_destroy(plan: int) -> None:
+    _check(_load().mpow_plan_destroy(plan), "mpow_plan_destroy")
+
+
+def mpow_run(plan: int, A: int, n: int, p: int, out: int, log2_scale: int | None,
+             stream: int | None) -> None:
+    st = _load().mpow_run(plan, A, int(n), int(p), out, log2_scale or None, stream or None)
+    _check(st, "mpow_run")
+
+
+def mpow_run_batched(plan: int, count: int, A_ptrs, ns, ps, out_ptrs, log2_scale: int | None,
+                     stream: int | None) -> None:
+    c = ctypes
+    a = (c.c_void_p * count)(*A_ptrs)
+    o = (c.c_void_p * count)(*out_ptrs)
+    nn = (c.c_int * count)(*[int(x) for x in ns])
+    pp = (c.c_int64 * count)(*[int(x) for x in ps])
+    st = _load().mpow_run_batched(plan, int(count), c.cast(a, c.c_void_p), c.cast(nn, c.c_void_p),
+                                  c.cast(pp, c.c_void_p), c.cast(o, c.c_void_p),
+                                  log2_scale or None, stream or None)
+    _check(st, "mpow_run_batched")
+
+
+def mpow_last_device_error(plan: int) -> int:
+    return int(_load().mpow_last_device_error(plan))
+
+
+def mpow_plan_timing(plan: int, kernel: int):
+    """(launches, total_ms, total_flop, kernel symbol name)"""
+    c = ctypes
+    l, m, f, nm = c.c_int64(), c.c_double(), c.c_double(), c.c_char_p()
+    _check(_load().mpow_plan_timing(plan, int(kernel), c.byref(l), c.byref(m), c.byref(f), c.byref(nm)),
+           "mpow_plan_timing")
+    return l.value, m.value, f.value, (nm.value.decode() if nm.value else None)
+
+
+def mpow_plan_timing_reset(plan: int) -> None:
+    _check(_load().mpow_plan_timing_reset(plan), "mpow_plan_timing_reset")
+
+
+# ---------------------------------------------------------------- torch helpers
+
+class Plan:
+    """Owns an mpow plan; usable as a context manager."""
+
+    def __init__(self, max_n: int, max_batch: int = 0, mode: int = MPOW_FP32, flags: int = 0,
+                 device: int | None = None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.max_n, self.max_batch, self.mode, self.flags = max_n, max_batch, mode, flags
+        self.handle = mpow_plan_create(self.device, max_n, max_batch, mode, flags)
+
+    def close(self):
+        if self.handle:
+            mpow_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_matrix(A):
+    import torch
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.float32 or not A.is_cuda:
+        raise TypeError("A must be a float32 CUDA (HIP) tensor")
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("A must be a contiguous square matrix")
+
+
+def run(A, p: int, plan: Plan | None = None, out=None, return_scale: bool = False, stream=None):
+    """A^p of a square float32 device tensor.
+
+    Returns `out` (A^p rounded to float32), or (M, s) with A^p = M * 2^s when
+    return_scale is true; s is a one-element float64 device tensor."""
+    import torch
+    _check_matrix(A)
+    n = A.shape[0]
+    own = plan is None
+    if own:
+        plan = Plan(n, device=A.device.index)
+    try:
+        if out is None:
+            out = torch.empty_like(A)
+        scale = torch.empty(1, dtype=torch.float64, device=A.device) if return_scale else None
+        st = torch.cuda.current_stream(A.device) if stream is None else stream
+        mpow_run(plan.handle, A.data_ptr(), n, p, out.data_ptr(),
+                 scale.data_ptr() if scale is not None else None, st.cuda_stream)
+        if own:
+            torch.cuda.synchronize(A.device)
+    finally:
+        if own:
+            plan.close()
+    return (out, scale) if return_scale else out

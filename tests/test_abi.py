@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol the header declares, rejects bad arguments before touching a
+device, and its exponent schedule agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1204_3052_amd import mpow
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpow.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mpow.LIB_PATH):
+        from paper_1204_3052_amd import build
+        build.build(verbose=False)
+    return mpow._load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpow_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    assert header_functions() == sorted(mpow.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(mpow.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(raw, name), name
+
+
+def test_status_strings(lib):
+    for code in range(6):
+        assert isinstance(mpow.mpow_status_str(code), str)
+    assert mpow.mpow_status_str(99) == "unknown status"
+
+
+@pytest.mark.parametrize("p", list(range(0, 200)) + [1000, 1023, 2 ** 20 - 1, 2 ** 20, 2 ** 62 + 5, 2 ** 63 - 1])
+def test_schedule_matches_oracle(lib, p):
+    ops = mpow.mpow_schedule(p)
+    assert ["S" if o == 0 else "M" for o in ops] == oracle.schedule(p)
+    assert mpow.mpow_gemm_count(p) == len(ops) == oracle.gemm_count(p)
+
+
+def test_schedule_rejects(lib):
+    assert lib.mpow_gemm_count(-1) == -1
+    assert lib.mpow_schedule(-5, None, 10) == -1
+    assert lib.mpow_schedule(17, None, 10) == -1   # ops NULL while G(17)=5 > 0
+    buf = (ctypes.c_uint8 * 4)()
+    assert lib.mpow_schedule(17, ctypes.cast(buf, ctypes.c_void_p), 4) == -1  # cap too small
+    assert lib.mpow_schedule(1, None, 0) == 0
+    assert lib.mpow_gemm_count(2 ** 63 - 1) == 124 <= mpow.MPOW_MAX_STEPS
+
+
+def test_workspace_bytes(lib):
+    assert mpow.mpow_workspace_bytes(0) == 0
+    assert mpow.mpow_workspace_bytes(16, -1) == 0
+    assert mpow.mpow_workspace_bytes(16, 0, 9) == 0
+    b = mpow.mpow_workspace_bytes(8192)
+    assert 2 * 8192 * 8192 * 4 <= b < 2 * 8192 * 8192 * 4 + 8 * 2 ** 20
+
+
+def test_null_arguments_rejected_without_device(lib):
+    P = ctypes.c_void_p
+    assert lib.mpow_plan_create(None, 0, 16, 0, 0, 0) == mpow.MPOW_ERR_INVALID
+    h = P()
+    assert lib.mpow_plan_create(ctypes.byref(h), 0, 0, 0, 0, 0) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_create(ctypes.byref(h), 0, 16, -1, 0, 0) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_create(ctypes.byref(h), 0, 16, 0, 7, 0) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_create(ctypes.byref(h), 0, 16, 0, 0, 1 << 10) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_run(None, 16, 4, 3, 16, None, None) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_run_batched(None, 1, None, None, None, None, None, None) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_timing(None, 0, None, None, None, None) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_timing_reset(None) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_destroy(None) == mpow.MPOW_SUCCESS
+    assert lib.mpow_last_device_error(None) == 0
+
+
+def test_plan_create_without_gpu_reports_device_error(lib):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    h = ctypes.c_void_p()
+    st = lib.mpow_plan_create(ctypes.byref(h), 0, 64, 0, 0, 0)
+    assert st == mpow.MPOW_ERR_DEVICE and not h.value
