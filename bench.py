@@ -68,7 +68,20 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (for HBM counter scaling)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "copies": 3}))
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
