@@ -46,9 +46,10 @@ bool sizes_for(int max_n, Sizes *z) {
     return true;
 }
 
-bool ranges_overlap(const void *a, const void *b, size_t bytes) {
+// [a, a + alen) and [b, b + blen) share at least one byte
+bool ranges_overlap(const void *a, size_t alen, const void *b, size_t blen) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-    return x < y + bytes && y < x + bytes;
+    return x < y + blen && y < x + alen;
 }
 
 int popcount64(uint64_t v) { return __builtin_popcountll(v); }
@@ -181,11 +182,12 @@ mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *
     if (!plan || !A || !out || n < 1 || p < 0) return MPOW_ERR_INVALID;
     if (n > plan->max_n) return MPOW_ERR_INVALID;
     const size_t bytes = (size_t)n * (size_t)n * sizeof(float);
-    if ((const void *)A != (const void *)out && ranges_overlap(A, out, bytes))
+    if ((const void *)A != (const void *)out && ranges_overlap(A, bytes, out, bytes))
         return MPOW_ERR_INVALID;
     if (((uintptr_t)A & 3) || ((uintptr_t)out & 3) || ((uintptr_t)log2_scale & 7))
         return MPOW_ERR_INVALID;
-    if (log2_scale && (ranges_overlap(log2_scale, A, bytes) || ranges_overlap(log2_scale, out, bytes)))
+    if (log2_scale && (ranges_overlap(log2_scale, sizeof(double), A, bytes) ||
+                       ranges_overlap(log2_scale, sizeof(double), out, bytes)))
         return MPOW_ERR_INVALID;
 
     hipStream_t s = (hipStream_t)stream;
