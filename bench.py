@@ -33,6 +33,26 @@ def gemm_count(p: int) -> int:
     return p.bit_length() - 1 + bin(p).count("1") - 1 if p >= 2 else 0
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None when the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_gemm_f32.txt")
+    src = os.path.join(ROOT, "paper_1204_3052_amd", "csrc", "gemm_f32.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(seconds_budget: float = 20.0):
     """The FP64 oracle on host cores over a bounded sample of the same workload."""
     import numpy as np
@@ -146,7 +166,7 @@ def main():
     achieved = (kflop / launches) / (kms / launches * 1e-3) / 1e12 if launches else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": kname, "launches": launches,
+                "traffic": measured_traffic(), "traffic_unit": "bytes/launch", "kernel": kname, "launches": launches,
                 "avg_launch_ms": round(kms / launches, 4) if launches else None}
     mpow.mpow_plan_destroy(plan)
 
