@@ -49,7 +49,14 @@ typedef enum mpow_status {
 } mpow_status;
 
 /* Arithmetic of the matrix products.  Inputs and outputs are float32 in every
- * mode.  MPOW_FP32: float32 MFMA products with float32 accumulation. */
+ * mode; scaling, the log2 scale and the final rescale are the same in all.
+ *  MPOW_FP32   float32 MFMA products with float32 accumulation.
+ *  MPOW_FP16X3 each scaled operand X' is split into FP16 hi = rn(X') and
+ *              lo = rn((X' - hi) 2^11); a product is hi.hi + 2^-11 (hi.lo +
+ *              lo.hi) from three FP16 MFMA products with float32
+ *              accumulation (about float32 accuracy).
+ *  MPOW_BF16X3 the same with BF16 halves and no lo shift (about 16 bits of
+ *              operand precision; looser tolerance). */
 typedef enum mpow_mode {
     MPOW_FP32 = 0,
     MPOW_FP16X3 = 1,
@@ -135,6 +142,8 @@ enum {
     MPOW_KERNEL_GEMM_F32_128 = 0, /* float32 product, 128x128 tiles */
     MPOW_KERNEL_GEMM_F32_64 = 1,  /* float32 product, 64x64 tiles */
     MPOW_KERNEL_GEMM_F32_32 = 2,  /* float32 product, 32x32 tiles */
+    MPOW_KERNEL_GEMM_F16X3_128 = 3,  /* FP16 hi/lo three-product, 128x128 tiles */
+    MPOW_KERNEL_GEMM_BF16X3_128 = 4, /* BF16 hi/lo three-product, 128x128 tiles */
     MPOW_KERNEL_COUNT = 8
 };
 

@@ -31,10 +31,10 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace sizes, in bytes, for a plan of max_n.
 struct Sizes {
-    size_t buf, part, partA, escale, total;
+    size_t buf, part, partA, escale, split, total;
 };
 
-bool sizes_for(int max_n, Sizes *z) {
+bool sizes_for(int max_n, int mode, Sizes *z) {
     if (max_n < 1) return false;
     const size_t n = (size_t)max_n;
     const size_t t32 = (n + 31) / 32;
@@ -42,7 +42,9 @@ bool sizes_for(int max_n, Sizes *z) {
     z->part = round_up(t32 * t32 * sizeof(double), 256);
     z->partA = round_up(512 * sizeof(double), 256);
     z->escale = round_up((MPOW_MAX_STEPS + 2) * sizeof(int), 256);
-    z->total = 2 * z->buf + 2 * z->part + z->partA + z->escale;
+    const size_t ld = (size_t)split_ld(max_n);
+    z->split = mode == MPOW_FP32 ? 0 : round_up(ld * ld * 2, 256);  // one 16-bit ld x ld array
+    z->total = 2 * z->buf + 2 * z->part + z->partA + z->escale + 8 * z->split;
     return true;
 }
 
@@ -63,6 +65,89 @@ hipEvent_t take_event(mpow_plan *plan) {
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
+}
+
+mpow_status record_start(mpow_plan *plan, int kernel, double flop, hipStream_t s, TimingRecord *rec) {
+    rec->kernel = kernel;
+    rec->flop = flop;
+    rec->start = take_event(plan);
+    rec->stop = take_event(plan);
+    if (!rec->start || !rec->stop) return device_error(plan, hipErrorOutOfMemory);
+    const hipError_t e = hipEventRecord(rec->start, s);
+    return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
+}
+
+mpow_status record_stop(mpow_plan *plan, TimingRecord *rec, hipStream_t s) {
+    const hipError_t e = hipEventRecord(rec->stop, s);
+    if (e != hipSuccess) return device_error(plan, e);
+    plan->pending.push_back(*rec);
+    return MPOW_SUCCESS;
+}
+
+// Split-precision power: A is split once (both layouts); after every product
+// but the last, the float32 result is split again with its own scale.
+mpow_status run_split(mpow_plan *plan, const float *A, int n, int64_t p, const uint8_t *ops, int G,
+                      int nbA, float *out, double *log2_scale, hipStream_t s) {
+    Workspace &ws = plan->ws;
+    const int mode = plan->mode;
+    const int ld = split_ld(n);
+    const bool timing = (plan->flags & MPOW_FLAG_TIMING) != 0;
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+    const int kernel = gemm_split_pick(mode, n);
+    const int tiles = gemm_split_tiles(kernel, n);
+
+    SplitLaunch sl;
+    sl.X = A;
+    sl.part = ws.partA;
+    sl.nPart = nbA;
+    sl.n = n;
+    sl.ld = ld;
+    sl.hi = ws.sa[0];
+    sl.lo = ws.sa[1];
+    sl.hiT = ws.sa[2];
+    sl.loT = ws.sa[3];
+    sl.eSlot = ws.escale;
+    hipError_t e = launch_split(mode, sl, s);
+    if (e != hipSuccess) return device_error(plan, e);
+
+    for (int k = 1; k <= G; ++k) {
+        void *const *xs = (k == 1) ? ws.sa : ws.sx;
+        void *const *ys = (ops[k - 1] == 0) ? xs : ws.sa;
+        SplitGemmLaunch g;
+        g.xh = xs[0];
+        g.xl = xs[1];
+        g.yh = ys[2];
+        g.yl = ys[3];
+        g.C = ws.buf[k & 1];
+        g.partC = ws.part[k & 1];
+        g.n = n;
+        g.ld = ld;
+        TimingRecord rec{};
+        if (timing) {
+            const mpow_status st = record_start(plan, kernel, flop, s, &rec);
+            if (st != MPOW_SUCCESS) return st;
+        }
+        e = gemm_split_launch(kernel, g, s);
+        if (e != hipSuccess) return device_error(plan, e);
+        if (timing) {
+            const mpow_status st = record_stop(plan, &rec, s);
+            if (st != MPOW_SUCCESS) return st;
+        }
+        if (k < G) {
+            sl.X = g.C;
+            sl.part = g.partC;
+            sl.nPart = tiles;
+            sl.hi = ws.sx[0];
+            sl.lo = ws.sx[1];
+            sl.hiT = ws.sx[2];
+            sl.loT = ws.sx[3];
+            sl.eSlot = ws.escale + k;
+            e = launch_split(mode, sl, s);
+            if (e != hipSuccess) return device_error(plan, e);
+        }
+    }
+    e = launch_finish(ws.buf[G & 1], n, ws.part[G & 1], tiles, ws.escale, p, G, out, log2_scale, s);
+    return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
 }
 
 }  // namespace
@@ -104,7 +189,7 @@ int mpow_schedule(int64_t p, uint8_t *ops, int cap) {
 
 size_t mpow_workspace_bytes(int max_n, int max_batch, int mode) {
     Sizes z;
-    if (max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 || !sizes_for(max_n, &z)) return 0;
+    if (max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 || !sizes_for(max_n, mode, &z)) return 0;
     return z.total;
 }
 
@@ -115,12 +200,11 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 ||
         (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON)) != 0)
         return MPOW_ERR_INVALID;
-    if (mode != MPOW_FP32) return MPOW_ERR_UNSUPPORTED;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return MPOW_ERR_DEVICE;
     Sizes z;
-    sizes_for(max_n, &z);
+    sizes_for(max_n, mode, &z);
 
     mpow_plan *plan = new (std::nothrow) mpow_plan();
     if (!plan) return MPOW_ERR_NOMEM;
@@ -155,6 +239,10 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     plan->ws.part[1] = (double *)q; q += z.part;
     plan->ws.partA = (double *)q; q += z.partA;
     plan->ws.escale = (int *)q; q += z.escale;
+    for (int k = 0; k < 4 && z.split; ++k) {
+        plan->ws.sx[k] = q; q += z.split;
+        plan->ws.sa[k] = q; q += z.split;
+    }
     plan->ws.part_cap = z.part / sizeof(double);
     plan->ws.partA_cap = z.partA / sizeof(double);
     *out_plan = plan;
@@ -207,6 +295,7 @@ mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *
 
     uint8_t ops[MPOW_MAX_STEPS];
     const int G = mpow_schedule(p, ops, MPOW_MAX_STEPS);
+    if (plan->mode != MPOW_FP32 && G > 0) return run_split(plan, A, n, p, ops, G, nbA, out, log2_scale, s);
     const int kernel = gemm_pick(n);
     const int tiles = gemm_tiles(kernel, n);
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
@@ -291,7 +380,7 @@ mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, do
     if (launches) *launches = plan->launches[kernel];
     if (total_ms) *total_ms = plan->ms[kernel];
     if (total_flop) *total_flop = plan->flop[kernel];
-    if (name) *name = gemm_name(kernel);
+    if (name) *name = gemm_name(kernel) ? gemm_name(kernel) : gemm_split_name(kernel);
     return MPOW_SUCCESS;
 }
 

@@ -19,6 +19,9 @@ namespace mpow {
 //  escale           escale[k] = floor(log2 ||C_k||_F) of the k-th product's
 //                   output (C_0 = A), written by the kernel that consumes C_k
 struct Workspace {
+    // split modes: hi/lo of the running matrix (row-major, transposed) and of A
+    void *sx[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *sa[4] = {nullptr, nullptr, nullptr, nullptr};
     float *buf[2] = {nullptr, nullptr};
     double *part[2] = {nullptr, nullptr};
     double *partA = nullptr;
@@ -40,6 +43,33 @@ struct GemmLaunch {
     int *eSlot;              // where block 0 records eX (may be null)
     int n;
 };
+
+// Split of a float32 matrix into 16-bit hi/lo, row-major and transposed,
+// zero-padded to ld x ld.
+struct SplitLaunch {
+    const float *X;
+    const double *part;   // partial sums of squares of X
+    int nPart;
+    int n, ld;
+    void *hi, *lo, *hiT, *loT;
+    int *eSlot;           // block (0,0) records e of X here (may be null)
+};
+
+// Split-precision product: C = (X'Y') * 2^-2k from the hi/lo halves.
+struct SplitGemmLaunch {
+    const void *xh, *xl;  // left operand, row-major, ld
+    const void *yh, *yl;  // right operand, transposed, ld
+    float *C;
+    double *partC;
+    int n, ld;
+};
+
+int split_ld(int n);
+hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s);
+int gemm_split_pick(int mode, int n);
+int gemm_split_tiles(int kernel, int n);
+const char *gemm_split_name(int kernel);
+hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s);
 
 // Product kernel variants (index = MPOW_KERNEL_* id).
 int gemm_pick(int n);                       // kernel id used for size n

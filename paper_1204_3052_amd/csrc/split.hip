@@ -1,0 +1,343 @@
+// Split-precision products (modes FP16X3 and BF16X3).
+//
+// Every float32 operand X is written as two 16-bit matrices,
+//   X' = X * 2^(k - e)          (e = floor(log2 ||X||_F), k a fixed shift)
+//   hi = rn16(X'),  lo = rn16((X' - hi) * 2^c)
+// so that X' = hi + 2^-c lo to about 22 bits (FP16, c = 11) or 16 bits
+// (BF16, c = 0).  A product then takes three 16-bit MFMA products with
+// float32 accumulation, dropping the lo*lo term:
+//   X'Y' ~= hi_X hi_Y + 2^-c (hi_X lo_Y + lo_X hi_Y).
+// FP16 keeps the cross terms in their own accumulators so that the 2^-c is
+// applied once, exactly, in float32 at the end; the fixed shift k = 14 puts
+// the largest entry of a normalised matrix (||X'||_F < 2^15) inside FP16
+// range while typical entries stay far above its subnormals.  BF16 has
+// float32's exponent range and needs neither shift.
+//
+// split_kernel turns a float32 matrix into hi/lo in two layouts: row-major
+// (the left operand: a lane reads 8 consecutive k of its row) and transposed
+// (the right operand: row j holds column j, so a lane again reads 8
+// consecutive k).  Both are zero-padded to ld = n rounded up to 128, so the
+// product kernel's loads need no bounds checks.
+#include "mpow_internal.h"
+#include "scale_device.h"
+
+namespace mpow {
+
+namespace {
+
+template <typename T>
+struct SplitTraits;
+template <>
+struct SplitTraits<_Float16> {
+    static constexpr int kShift = 14;
+    static constexpr int loShift = 11;
+    static constexpr bool twoAcc = true;
+};
+template <>
+struct SplitTraits<__bf16> {
+    static constexpr int kShift = 0;
+    static constexpr int loShift = 0;
+    static constexpr bool twoAcc = false;
+};
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Vec8;
+template <>
+struct Vec8<_Float16> {
+    typedef h8 type;
+};
+template <>
+struct Vec8<__bf16> {
+    typedef b8 type;
+};
+
+template <typename T>
+__device__ __forceinline__ v16f mfma16(typename Vec8<T>::type a, typename Vec8<T>::type b, v16f c);
+template <>
+__device__ __forceinline__ v16f mfma16<_Float16>(h8 a, h8 b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ v16f mfma16<__bf16>(b8 a, b8 b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ split
+
+constexpr int STS = 64;  // split tile edge
+
+template <typename T>
+__global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
+    typedef SplitTraits<T> Tr;
+    __shared__ double red[256];
+    __shared__ T th[STS][STS + 8];
+    __shared__ T tl[STS][STS + 8];
+    const int tid = threadIdx.x;
+    const int n = s.n, ld = s.ld;
+    const int eX = exponent_of_sumsq(block_sum_partials<256>(s.part, s.nPart, red));
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && s.eSlot) *s.eSlot = eX;
+    const PowScale f = pow2_neg(eX - Tr::kShift);
+    const float cScale = (float)(1 << Tr::loShift);
+    const int r0 = blockIdx.y * STS, c0 = blockIdx.x * STS;
+    const bool vec = (n % 4) == 0;
+
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = tid / 16 + 16 * q, c = (tid % 16) * 4;
+        const int gr = r0 + r, gc = c0 + c;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (gr < n) {
+            if (vec && gc + 3 < n) {
+                const f4 x = *(const f4 *)(s.X + (int64_t)gr * n + gc);
+                v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (gc + t < n) v[t] = s.X[(int64_t)gr * n + gc + t];
+            }
+        }
+        T h[4], l[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float x = v[t] * f.a * f.b;
+            h[t] = (T)x;
+            l[t] = (T)((x - (float)h[t]) * cScale);
+            th[r][c + t] = h[t];
+            tl[r][c + t] = l[t];
+        }
+        T *hp = (T *)s.hi + (int64_t)gr * ld + gc;
+        T *lp = (T *)s.lo + (int64_t)gr * ld + gc;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            hp[t] = h[t];
+            lp[t] = l[t];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = tid / 16 + 16 * q, r = (tid % 16) * 4;
+        T *hp = (T *)s.hiT + (int64_t)(c0 + c) * ld + r0 + r;
+        T *lp = (T *)s.loT + (int64_t)(c0 + c) * ld + r0 + r;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            hp[t] = th[r + t][c];
+            lp[t] = tl[r + t][c];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ product
+
+constexpr int SBK = 32;        // K extent (16-bit elements) of one LDS tile
+constexpr int SLD = SBK + 8;   // LDS row stride, conflict-free 16-byte reads
+
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch g) {
+    typedef SplitTraits<T> Tr;
+    typedef typename Vec8<T>::type V8;
+    constexpr int NT = WM * WN * 64;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 32, FN = TN / 32;
+    constexpr int NACC = Tr::twoAcc ? 2 : 1;
+
+    __shared__ __attribute__((aligned(16))) T Ah[2][BM * SLD];
+    __shared__ __attribute__((aligned(16))) T Al[2][BM * SLD];
+    __shared__ __attribute__((aligned(16))) T Bh[2][BN * SLD];
+    __shared__ __attribute__((aligned(16))) T Bl[2][BN * SLD];
+    __shared__ double red[WM * WN];
+
+    const int n = g.n, ld = g.ld;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int grp = lane >> 5, l32 = lane & 31;
+    const int tilesN = (n + BN - 1) / BN;
+    const int tile = blockIdx.x;
+    const int m0 = (tile / tilesN) * BM;
+    const int n0 = (tile % tilesN) * BN;
+
+    // 16-byte chunks: a tile row of SBK elements is SBK/8 chunks.
+    constexpr int CPR = SBK / 8;
+    constexpr int LA = BM * CPR / NT;
+    constexpr int LB = BN * CPR / NT;
+    static_assert(LA * NT == BM * CPR && LB * NT == BN * CPR, "load split");
+    u4 rah[LA], ral[LA], rbh[LB], rbl[LB];
+    const T *__restrict__ xh = (const T *)g.xh;
+    const T *__restrict__ xl = (const T *)g.xl;
+    const T *__restrict__ yh = (const T *)g.yh;
+    const T *__restrict__ yl = (const T *)g.yl;
+
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int idx = tid + r * NT;
+            const int row = idx / CPR, c = (idx % CPR) * 8;
+            const int64_t off = (int64_t)(m0 + row) * ld + k0 + c;
+            rah[r] = *(const u4 *)(xh + off);
+            ral[r] = *(const u4 *)(xl + off);
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int idx = tid + r * NT;
+            const int row = idx / CPR, c = (idx % CPR) * 8;
+            const int64_t off = (int64_t)(n0 + row) * ld + k0 + c;
+            rbh[r] = *(const u4 *)(yh + off);
+            rbl[r] = *(const u4 *)(yl + off);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int idx = tid + r * NT;
+            const int row = idx / CPR, c = (idx % CPR) * 8;
+            *(u4 *)(&Ah[buf][row * SLD + c]) = rah[r];
+            *(u4 *)(&Al[buf][row * SLD + c]) = ral[r];
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int idx = tid + r * NT;
+            const int row = idx / CPR, c = (idx % CPR) * 8;
+            *(u4 *)(&Bh[buf][row * SLD + c]) = rbh[r];
+            *(u4 *)(&Bl[buf][row * SLD + c]) = rbl[r];
+        }
+    };
+
+    v16f acc[NACC][FM][FN];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][i][j][r] = 0.f;
+
+    // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 128).
+    const int nk = (n + SBK - 1) / SBK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * SBK);
+#pragma unroll
+        for (int s = 0; s < SBK / 16; ++s) {
+            V8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int off = (wm * TM + i * 32 + l32) * SLD + s * 16 + grp * 8;
+                ah[i] = *(const V8 *)(&Ah[cur][off]);
+                al[i] = *(const V8 *)(&Al[cur][off]);
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int off = (wn * TN + j * 32 + l32) * SLD + s * 16 + grp * 8;
+                bh[j] = *(const V8 *)(&Bh[cur][off]);
+                bl[j] = *(const V8 *)(&Bl[cur][off]);
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[0][i][j] = mfma16<T>(ah[i], bh[j], acc[0][i][j]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[NACC - 1][i][j] = mfma16<T>(ah[i], bl[j], acc[NACC - 1][i][j]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[NACC - 1][i][j] = mfma16<T>(al[i], bh[j], acc[NACC - 1][i][j]);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+
+    // C = (hh + 2^-c cross) * 2^-2k, both factors exact powers of two.
+    const float cross = 1.0f / (float)(1 << Tr::loShift);
+    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
+    double ss = 0.0;
+    float *__restrict__ C = g.C;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
+                const int col = n0 + wn * TN + j * 32 + l32;
+                float v = acc[0][i][j][r];
+                if (Tr::twoAcc) v = v + acc[NACC - 1][i][j][r] * cross;
+                v *= outScale;
+                if (row < n && col < n) {
+                    C[(int64_t)row * n + col] = v;
+                    ss += (double)v * (double)v;
+                }
+            }
+    ss = wave_sum_lane0(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < WM * WN; ++w) t += red[w];
+        g.partC[tile] = t;
+    }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+hipError_t launch_gemm_split(const SplitGemmLaunch &g, hipStream_t s) {
+    const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_split_kernel<T, BM, BN, WM, WN>), dim3(tiles), dim3(WM * WN * 64), 0,
+                       s, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int split_ld(int n) { return (n + 127) / 128 * 128; }
+
+hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
+    const int t = sl.ld / STS;
+    if (mode == MPOW_FP16X3)
+        hipLaunchKernelGGL(split_kernel<_Float16>, dim3(t, t), dim3(256), 0, s, sl);
+    else
+        hipLaunchKernelGGL(split_kernel<__bf16>, dim3(t, t), dim3(256), 0, s, sl);
+    return hipGetLastError();
+}
+
+int gemm_split_pick(int mode, int n) {
+    (void)n;
+    return mode == MPOW_FP16X3 ? MPOW_KERNEL_GEMM_F16X3_128 : MPOW_KERNEL_GEMM_BF16X3_128;
+}
+
+int gemm_split_tiles(int kernel, int n) {
+    (void)kernel;
+    const int t = (n + 127) / 128;
+    return t * t;
+}
+
+const char *gemm_split_name(int kernel) {
+    if (kernel == MPOW_KERNEL_GEMM_F16X3_128) return "gemm_split_kernel<_Float16,128,128,2,2>";
+    if (kernel == MPOW_KERNEL_GEMM_BF16X3_128) return "gemm_split_kernel<__bf16,128,128,2,2>";
+    return nullptr;
+}
+
+hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s) {
+    switch (kernel) {
+        case MPOW_KERNEL_GEMM_F16X3_128: return launch_gemm_split<_Float16, 128, 128, 2, 2>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_128: return launch_gemm_split<__bf16, 128, 128, 2, 2>(g, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mpow

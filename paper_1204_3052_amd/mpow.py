@@ -32,6 +32,8 @@ MPOW_MAX_STEPS = 126
 MPOW_KERNEL_GEMM_F32_128 = 0
 MPOW_KERNEL_GEMM_F32_64 = 1
 MPOW_KERNEL_GEMM_F32_32 = 2
+MPOW_KERNEL_GEMM_F16X3_128 = 3
+MPOW_KERNEL_GEMM_BF16X3_128 = 4
 MPOW_KERNEL_COUNT = 8
 
 # every symbol include/mpow.h declares
@@ -56,6 +58,13 @@ def _load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1204_3052_amd.build`")
+    # One HIP runtime per process: when PyTorch is present, load its runtime
+    # first so that the library's libamdhip64.so.7 dependency resolves to the
+    # copy torch uses (a second runtime would not see the GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     c = ctypes
     P = c.c_void_p

@@ -16,10 +16,20 @@ from paper_1204_3052_amd import inputs, mpow
 
 FP32_ABS_TOL = 1e-5
 FP32_FLOOR_FACTOR = 64.0
+# BF16 hi/lo halves carry about 16 bits of each operand: a looser stated bound.
+BF16X3_ABS_TOL = 2e-4
+BF16X3_FLOOR_FACTOR = 1024.0
 
 
 def tol_fp32(floor: float) -> float:
     return max(FP32_ABS_TOL, FP32_FLOOR_FACTOR * floor)
+
+
+def tol_mode(mode: int, floor: float) -> float:
+    """Stated tolerance per product mode (FP16X3 shares the float32 bound)."""
+    if mode == mpow.MPOW_BF16X3:
+        return max(BF16X3_ABS_TOL, BF16X3_FLOOR_FACTOR * floor)
+    return tol_fp32(floor)
 
 
 def run_gpu(plan_handle: int, A_np: np.ndarray, p: int, log_scale: bool = True, out_is_input=False):
