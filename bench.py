@@ -82,12 +82,65 @@ def cpu_baseline(seconds_budget: float = 20.0):
                       + f"; {dt:.1f} s"}
 
 
+def split_workload(args):
+    """FP32 vs the two split-precision modes on N=4096, p in {64, 1000}.
+    Same effective-flop formula for every mode; each result's relative
+    Frobenius error against the FP64 oracle is reported beside its rate."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1204_3052_amd import inputs, mpow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = 4096
+    A_np = inputs.gaussian(n, 4)
+    A = torch.from_numpy(A_np).to(dev)
+    out = torch.empty_like(A)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    refs = {p: oracle.mpow_binary(A_np, p) for p in (64, 1000)}
+    for name, mode in (("fp32", mpow.MPOW_FP32), ("fp16x3", mpow.MPOW_FP16X3), ("bf16x3", mpow.MPOW_BF16X3)):
+        plan = mpow.mpow_plan_create(0, n, 0, mode, 0)
+        for p in (64, 1000):
+            run = lambda: mpow.mpow_run(plan, A.data_ptr(), n, p, out.data_ptr(), sc.data_ptr(),
+                                        stream.cuda_stream)
+            for _ in range(args.warmup):
+                run()
+            torch.cuda.synchronize(dev)
+            times = []
+            for _ in range(max(args.steps, 1)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                run()
+                e1.record(stream)
+                torch.cuda.synchronize(dev)
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            err = oracle.rel_err(out.cpu().numpy(), float(sc.item()), *refs[p])
+            rows.append({"mode": name, "n": n, "p": p, "ms": round(ms, 3),
+                         "gflops": round(gemm_count(p) * 2.0 * n ** 3 / ms / 1e6, 1),
+                         "rel_err": float(f"{err:.3e}")})
+        mpow.mpow_plan_destroy(plan)
+    fp32 = {r["p"]: r["ms"] for r in rows if r["mode"] == "fp32"}
+    for r in rows:
+        r["speedup_vs_fp32"] = round(fp32[r["p"]] / r["ms"], 3)
+    print(json.dumps({"workload": "split precision, N=4096 N(0,1)/sqrt(N), p in {64,1000}",
+                      "unit": "GFLOP/s (FP32-equivalent, G(p)*2N^3)", "results": rows}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="plain", choices=["plain", "split"],
+                    help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
+                         "at N=4096, p in {64, 1000}, with errors against the oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -108,6 +161,9 @@ def main():
                                    "multi-GPU sharding is a design note, not built",
                           "n_gpus": args.gpus}))
         return 2
+
+    if args.workload == "split":
+        return split_workload(args)
 
     import numpy as np
     import torch
