@@ -132,13 +132,77 @@ def split_workload(args):
     return 0
 
 
+def batched_workload(args):
+    """4096 ragged matrices (N uniform on multiples of 16 in [16,256], p
+    log-uniform in [2,1000], N(0,1)/sqrt(N)) in one graph-replayed persistent
+    launch, against a loop of plain mpow_run calls over the same matrices."""
+    import numpy as np
+    import torch
+
+    from paper_1204_3052_amd import inputs, mpow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    count = 4096
+    ns, ps = inputs.ragged_batch(count, 3)
+    offs, o = [], 0
+    for n in ns:
+        offs.append(o)
+        o += (int(n) * int(n) + 63) // 64 * 64
+    host = np.zeros(o, np.float32)
+    for i, (n, off) in enumerate(zip(ns, offs)):
+        host[off:off + n * n] = inputs.gaussian(int(n), 50000 + i).ravel()
+    A = torch.from_numpy(host).to(dev)
+    out = torch.empty_like(A)
+    sc = torch.zeros(count, dtype=torch.float64, device=dev)
+    a_ptrs = [A.data_ptr() + 4 * off for off in offs]
+    o_ptrs = [out.data_ptr() + 4 * off for off in offs]
+    stream = torch.cuda.current_stream(dev)
+    flop = float(sum(gemm_count(int(p)) * 2.0 * int(n) ** 3 for n, p in zip(ns, ps)))
+    hb = mpow.mpow_plan_create(0, 256, count, mpow.MPOW_FP32, 0)
+    hp = mpow.mpow_plan_create(0, 256, 0, mpow.MPOW_FP32, 0)
+    nl, pl = [int(x) for x in ns], [int(x) for x in ps]
+
+    def batched():
+        mpow.mpow_run_batched(hb, count, a_ptrs, nl, pl, o_ptrs, sc.data_ptr(), stream.cuda_stream)
+
+    def looped():
+        for i in range(count):
+            mpow.mpow_run(hp, a_ptrs[i], nl[i], pl[i], o_ptrs[i], sc[i:i + 1].data_ptr(), stream.cuda_stream)
+
+    res = {}
+    for name, fn in (("batched", batched), ("loop_plain", looped)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize(dev)
+        times = []
+        for _ in range(max(args.steps, 1)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize(dev)
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        res[name] = {"ms": round(ms, 3), "gflops": round(flop / ms / 1e6, 1),
+                     "pct_fp32_mfma_peak": round(flop / ms / 1e6 / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2)}
+    mpow.mpow_plan_destroy(hb)
+    mpow.mpow_plan_destroy(hp)
+    print(json.dumps({"workload": "ragged batch: 4096 FP32 matrices, N in {16..256} step 16, "
+                                  "p log-uniform [2,1000], one persistent graph-replayed launch",
+                      "effective_gflop_per_batch": round(flop / 1e9, 2), "results": res,
+                      "speedup_vs_loop": round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)}),
+          flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="plain", choices=["plain", "split"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
                          "at N=4096, p in {64, 1000}, with errors against the oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -164,6 +228,8 @@ def main():
 
     if args.workload == "split":
         return split_workload(args)
+    if args.workload == "batched":
+        return batched_workload(args)
 
     import numpy as np
     import torch

@@ -1,8 +1,10 @@
 // C ABI of the library: argument checks, the product schedule of p, plan and
 // workspace ownership, and the enqueueing of one power.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "mpow_internal.h"
 
@@ -31,10 +33,16 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace sizes, in bytes, for a plan of max_n.
 struct Sizes {
-    size_t buf, part, partA, escale, split, total;
+    size_t buf, part, partA, escale, split, desc, scratch, total;
 };
 
-bool sizes_for(int max_n, int mode, Sizes *z) {
+constexpr int kWorkersForSizing = 512;  // 256 CUs x 2 resident workers
+
+size_t batch_desc_bytes(int max_batch) {
+    return sizeof(BatchHeader) + (size_t)max_batch * sizeof(BatchItem);
+}
+
+bool sizes_for(int max_n, int max_batch, int mode, int workers, Sizes *z) {
     if (max_n < 1) return false;
     const size_t n = (size_t)max_n;
     const size_t t32 = (n + 31) / 32;
@@ -44,7 +52,10 @@ bool sizes_for(int max_n, int mode, Sizes *z) {
     z->escale = round_up((MPOW_MAX_STEPS + 2) * sizeof(int), 256);
     const size_t ld = (size_t)split_ld(max_n);
     z->split = mode == MPOW_FP32 ? 0 : round_up(ld * ld * 2, 256);  // one 16-bit ld x ld array
-    z->total = 2 * z->buf + 2 * z->part + z->partA + z->escale + 8 * z->split;
+    const size_t bmax = (size_t)(max_n < kBatchMaxN ? max_n : kBatchMaxN);
+    z->desc = max_batch > 0 ? round_up(batch_desc_bytes(max_batch), 256) : 0;
+    z->scratch = max_batch > 0 ? round_up((size_t)workers * 2 * bmax * bmax * sizeof(float), 256) : 0;
+    z->total = 2 * z->buf + 2 * z->part + z->partA + z->escale + 8 * z->split + z->desc + z->scratch;
     return true;
 }
 
@@ -189,7 +200,9 @@ int mpow_schedule(int64_t p, uint8_t *ops, int cap) {
 
 size_t mpow_workspace_bytes(int max_n, int max_batch, int mode) {
     Sizes z;
-    if (max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 || !sizes_for(max_n, mode, &z)) return 0;
+    if (max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 ||
+        !sizes_for(max_n, max_batch, mode, kWorkersForSizing, &z))
+        return 0;
     return z.total;
 }
 
@@ -203,8 +216,18 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return MPOW_ERR_DEVICE;
+    int workers = 0;
+    if (max_batch > 0) {
+        DeviceGuard g0(device);
+        int cus = 0;
+        if (!g0.ok || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
+                          hipSuccess)
+            return MPOW_ERR_DEVICE;
+        workers = cus * batched_occupancy();
+        if (workers < 1) workers = 1;
+    }
     Sizes z;
-    sizes_for(max_n, mode, &z);
+    sizes_for(max_n, max_batch, mode, workers, &z);
 
     mpow_plan *plan = new (std::nothrow) mpow_plan();
     if (!plan) return MPOW_ERR_NOMEM;
@@ -243,6 +266,26 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
         plan->ws.sx[k] = q; q += z.split;
         plan->ws.sa[k] = q; q += z.split;
     }
+    if (max_batch > 0) {
+        plan->batch_desc = q; q += z.desc;
+        plan->batch_scratch = (float *)q; q += z.scratch;
+        const int bmax = max_n < kBatchMaxN ? max_n : kBatchMaxN;
+        plan->batch_slot_floats = (int64_t)bmax * bmax;
+        plan->batch_workers = workers;
+        for (int b = 0; b <= kBatchMaxN / 16; ++b) plan->batch_cfg[b] = batched_cfg_for(b * 16);
+        bool ok = hipHostMalloc(&plan->batch_host, batch_desc_bytes(max_batch), hipHostMallocDefault) ==
+                  hipSuccess;
+        ok = ok && hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&plan->batch_done, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            if (plan->batch_host) (void)hipHostFree(plan->batch_host);
+            if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+            (void)hipFree(base);
+            delete plan;
+            return MPOW_ERR_NOMEM;
+        }
+    }
     plan->ws.part_cap = z.part / sizeof(double);
     plan->ws.partA_cap = z.partA / sizeof(double);
     *out_plan = plan;
@@ -258,6 +301,10 @@ mpow_status mpow_plan_destroy(mpow_plan_t plan) {
         (void)hipEventDestroy(r.stop);
     }
     for (auto e : plan->free_events) (void)hipEventDestroy(e);
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->batch_done) (void)hipEventDestroy(plan->batch_done);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    if (plan->batch_host) (void)hipHostFree(plan->batch_host);
     (void)hipFree(plan->ws.buf[0]);
     delete plan;
     return MPOW_SUCCESS;
@@ -354,9 +401,90 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
                              void *stream) {
     if (!plan || count < 0 || count > plan->max_batch) return MPOW_ERR_INVALID;
     if (count > 0 && (!A || !n || !p || !out)) return MPOW_ERR_INVALID;
-    (void)log2_scale;
-    (void)stream;
-    return MPOW_ERR_UNSUPPORTED;
+    if ((uintptr_t)log2_scale & 7) return MPOW_ERR_INVALID;
+    for (int i = 0; i < count; ++i) {
+        const int ni = n[i];
+        if (!A[i] || !out[i] || ni < 1 || ni > plan->max_n || ni > kBatchMaxN || p[i] < 0)
+            return MPOW_ERR_INVALID;
+        if (((uintptr_t)A[i] & 3) || ((uintptr_t)out[i] & 3)) return MPOW_ERR_INVALID;
+        const size_t bytes = (size_t)ni * (size_t)ni * sizeof(float);
+        if ((const void *)A[i] != (const void *)out[i] && ranges_overlap(A[i], bytes, out[i], bytes))
+            return MPOW_ERR_INVALID;
+    }
+    if (count == 0) return MPOW_SUCCESS;
+    if (plan->mode != MPOW_FP32) return MPOW_ERR_UNSUPPORTED;
+
+    hipStream_t s = (hipStream_t)stream;
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return device_error(plan, hipErrorInvalidDevice);
+    hipError_t e;
+    // The graph's copy reads the pinned descriptors: wait until the previous
+    // batch's copy has consumed them before rewriting.
+    if (plan->batch_pending) {
+        e = hipEventSynchronize(plan->batch_done);
+        if (e != hipSuccess) return device_error(plan, e);
+        plan->batch_pending = false;
+    }
+
+    // Longest work first: estimated work G(p) * n^3, ties by input order.
+    std::vector<int> order(count);
+    std::vector<double> work(count);
+    for (int i = 0; i < count; ++i) {
+        order[i] = i;
+        const double nn = (double)n[i];
+        work[i] = (double)(mpow_gemm_count(p[i]) + 1) * nn * nn * nn;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    BatchHeader *hdr = (BatchHeader *)plan->batch_host;
+    hdr->counter = 0;
+    hdr->count = count;
+    hdr->pad[0] = hdr->pad[1] = 0;
+    BatchItem *items = (BatchItem *)(hdr + 1);
+    for (int k = 0; k < count; ++k) {
+        const int i = order[k];
+        items[k].A = A[i];
+        items[k].out = out[i];
+        items[k].scale = log2_scale ? log2_scale + i : nullptr;
+        items[k].p = p[i];
+        items[k].n = n[i];
+        items[k].cfg = plan->batch_cfg[(n[i] + 15) / 16];
+    }
+
+    if (!plan->graph_exec || plan->graph_count != count) {
+        if (plan->graph_exec) {
+            (void)hipGraphExecDestroy(plan->graph_exec);
+            plan->graph_exec = nullptr;
+        }
+        BatchLaunch bl;
+        bl.desc = plan->batch_desc;
+        bl.scratch = plan->batch_scratch;
+        bl.slot_floats = plan->batch_slot_floats;
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return device_error(plan, e);
+        const hipError_t e1 = hipMemcpyAsync(plan->batch_desc, plan->batch_host,
+                                             batch_desc_bytes(count), hipMemcpyHostToDevice,
+                                             plan->capture_stream);
+        const hipError_t e2 = launch_batched(bl, plan->batch_workers, plan->capture_stream);
+        e = hipStreamEndCapture(plan->capture_stream, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return device_error(plan, e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e));
+        }
+        e = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            plan->graph_exec = nullptr;
+            return device_error(plan, e);
+        }
+        plan->graph_count = count;
+    }
+    e = hipGraphLaunch(plan->graph_exec, s);
+    if (e != hipSuccess) return device_error(plan, e);
+    e = hipEventRecord(plan->batch_done, s);
+    if (e != hipSuccess) return device_error(plan, e);
+    plan->batch_pending = true;
+    return MPOW_SUCCESS;
 }
 
 mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, double *total_ms,

@@ -71,6 +71,31 @@ int gemm_split_tiles(int kernel, int n);
 const char *gemm_split_name(int kernel);
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s);
 
+// Ragged batch: descriptors the host fills (sorted by work), a header with
+// the claim counter, and per-worker scratch.
+struct BatchHeader {
+    int counter;  // next descriptor to claim; the host copy resets it to 0
+    int count;
+    int pad[2];
+};
+struct BatchItem {
+    const float *A;
+    float *out;
+    double *scale;  // null: no log2 scale for this matrix
+    int64_t p;
+    int n;
+    int cfg;        // tile shape id (0: 128x128, 1: 64x64)
+};
+struct BatchLaunch {
+    void *desc;           // BatchHeader followed by the items
+    float *scratch;       // grid * 2 * slot_floats floats
+    int64_t slot_floats;  // floats per scratch buffer (max batched n squared)
+};
+constexpr int kBatchMaxN = 256;
+int batched_cfg_for(int n);
+int batched_occupancy();  // resident workers per CU
+hipError_t launch_batched(const BatchLaunch &b, int grid, hipStream_t s);
+
 // Product kernel variants (index = MPOW_KERNEL_* id).
 int gemm_pick(int n);                       // kernel id used for size n
 int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
@@ -86,6 +111,8 @@ hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
                          double *log2_scale, hipStream_t s);
 
 }  // namespace mpow
+
+using mpow::kBatchMaxN;
 
 struct TimingRecord {
     int kernel;
@@ -107,4 +134,16 @@ struct mpow_plan {
     int64_t launches[MPOW_KERNEL_COUNT] = {};
     double ms[MPOW_KERNEL_COUNT] = {};
     double flop[MPOW_KERNEL_COUNT] = {};
+    // ragged batch (max_batch > 0)
+    void *batch_desc = nullptr;    // device: BatchHeader + max_batch items
+    void *batch_host = nullptr;    // pinned host copy the graph's memcpy reads
+    float *batch_scratch = nullptr;
+    int64_t batch_slot_floats = 0;
+    int batch_workers = 0;
+    int batch_cfg[kBatchMaxN / 16 + 1] = {};  // tile shape per n bucket ((n+15)/16)
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_count = -1;
+    hipEvent_t batch_done = nullptr;
+    bool batch_pending = false;
 };
