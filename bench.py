@@ -161,6 +161,11 @@ def batched_workload(args):
     flop = float(sum(gemm_count(int(p)) * 2.0 * int(n) ** 3 for n, p in zip(ns, ps)))
     hb = mpow.mpow_plan_create(0, 256, count, mpow.MPOW_FP32, 0)
     hp = mpow.mpow_plan_create(0, 256, 0, mpow.MPOW_FP32, 0)
+    default_table = mpow.mpow_plan_tile_table(hb)
+    t0 = time.perf_counter()
+    mpow.mpow_plan_autotune(hb, None, mpow.MPOW_TUNE_FORCE)
+    tune_s = time.perf_counter() - t0
+    tuned_table = mpow.mpow_plan_tile_table(hb)
     nl, pl = [int(x) for x in ns], [int(x) for x in ps]
 
     def batched():
@@ -171,7 +176,12 @@ def batched_workload(args):
             mpow.mpow_run(hp, a_ptrs[i], nl[i], pl[i], o_ptrs[i], sc[i:i + 1].data_ptr(), stream.cuda_stream)
 
     res = {}
-    for name, fn in (("batched", batched), ("loop_plain", looped)):
+    def batched_default():
+        mpow.mpow_plan_tile_table(hb, default_table)
+        batched()
+        mpow.mpow_plan_tile_table(hb, tuned_table)
+
+    for name, fn in (("batched", batched), ("batched_untuned", batched_default), ("loop_plain", looped)):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize(dev)
@@ -191,6 +201,8 @@ def batched_workload(args):
     print(json.dumps({"workload": "ragged batch: 4096 FP32 matrices, N in {16..256} step 16, "
                                   "p log-uniform [2,1000], one persistent graph-replayed launch",
                       "effective_gflop_per_batch": round(flop / 1e9, 2), "results": res,
+                      "tile_table": {"tuned": tuned_table[1:], "default": default_table[1:],
+                                     "tune_seconds": round(tune_s, 2)},
                       "speedup_vs_loop": round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)}),
           flush=True)
     return 0

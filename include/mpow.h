@@ -134,6 +134,28 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
                              const int64_t *p, float *const *out, double *log2_scale,
                              void *stream);
 
+/* Tile table of the batched kernel: table[b] is the tile shape used for
+ * matrices with n in (16(b-1), 16b], b = 1..16 (table[0] is unused); shapes
+ * 0 = 128x128, 1 = 64x64, 2 = 128x64, 3 = 64x128.  Every shape gives
+ * bit-identical results; only speed differs.  set = 0 copies the plan's table
+ * into table[0..16]; set = 1 replaces it.  len must be >= 17.
+ * Errors: INVALID (plan NULL or without batch support, len < 17, a shape
+ * outside 0..3). */
+mpow_status mpow_plan_tile_table(mpow_plan_t plan, int *table, int len, int set);
+
+#define MPOW_TUNE_FORCE 1u /* ignore an existing cache file */
+
+/* Autotuner (precedent: the per-problem tile choice of section 4.3.7): for
+ * every size bucket up to min(max_n, 256) times each tile shape of the
+ * batched kernel on a synthetic batch that fills all workers (p = 3) and keeps
+ * the fastest in the plan's tile table.  If cache_path is non-NULL and holds
+ * a table written for the same GPU model (architecture and CU count), that
+ * table is loaded instead (unless MPOW_TUNE_FORCE); a fresh table is written
+ * there.  Synchronous; allocates temporary device memory (not on the run
+ * path).  Errors: INVALID (plan without batch support, unknown flags),
+ * UNSUPPORTED (mode other than MPOW_FP32), NOMEM, DEVICE. */
+mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_t flags);
+
 /* The last hipError_t value a call on this plan saw (0 if none). */
 int mpow_last_device_error(mpow_plan_t plan);
 

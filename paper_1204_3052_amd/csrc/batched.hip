@@ -62,15 +62,25 @@ __device__ double wg_product(const float *X, int eX, const float *Y, int eY, flo
     return S;
 }
 
+// Tile shape ids: 0 = 128x128, 1 = 64x64, 2 = 128x64, 3 = 64x128 (all with
+// 2x2 waves); every shape gives bit-identical products.
 __device__ double product_dispatch(int cfg, bool vec, const float *X, int eX, const float *Y,
                                    int eY, float *C, int n, float *As, float *Bs, double *red,
                                    double *bcast) {
-    if (cfg == 0) {
-        return vec ? wg_product<128, 128, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
-                   : wg_product<128, 128, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
+    switch (cfg) {
+        case 0:
+            return vec ? wg_product<128, 128, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
+                       : wg_product<128, 128, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
+        case 2:
+            return vec ? wg_product<128, 64, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
+                       : wg_product<128, 64, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
+        case 3:
+            return vec ? wg_product<64, 128, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
+                       : wg_product<64, 128, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
+        default:
+            return vec ? wg_product<64, 64, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
+                       : wg_product<64, 64, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
     }
-    return vec ? wg_product<64, 64, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
-               : wg_product<64, 64, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
 }
 
 __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
@@ -152,7 +162,12 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
 
 }  // namespace
 
-int batched_cfg_for(int n) { return n > 64 ? 0 : 1; }
+// Default tile shape before tuning: the one that pads n least, larger on ties.
+int batched_cfg_for(int n) {
+    if (n <= 64) return 1;
+    const int p128 = (n + 127) / 128 * 128, p64 = (n + 63) / 64 * 64;
+    return p128 * p128 <= p64 * p64 ? 0 : 1;
+}
 
 int batched_occupancy() {
     int blocks = 0;

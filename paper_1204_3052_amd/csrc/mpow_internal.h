@@ -84,7 +84,7 @@ struct BatchItem {
     double *scale;  // null: no log2 scale for this matrix
     int64_t p;
     int n;
-    int cfg;        // tile shape id (0: 128x128, 1: 64x64)
+    int cfg;        // tile shape id (0: 128x128, 1: 64x64, 2: 128x64, 3: 64x128)
 };
 struct BatchLaunch {
     void *desc;           // BatchHeader followed by the items

@@ -27,6 +27,8 @@ MPOW_BF16X3 = 2
 
 MPOW_FLAG_TIMING = 1
 MPOW_FLAG_POISON = 2
+MPOW_TUNE_FORCE = 1
+TILE_TABLE_LEN = 17
 MPOW_MAX_STEPS = 126
 
 MPOW_KERNEL_GEMM_F32_128 = 0
@@ -41,6 +43,7 @@ EXPORTS = (
     "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_workspace_bytes",
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_batched",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
+    "mpow_plan_tile_table", "mpow_plan_autotune",
 )
 
 _lib = None
@@ -81,6 +84,8 @@ def _load():
         "mpow_plan_timing": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_double),
                                        c.POINTER(c.c_double), c.POINTER(c.c_char_p)]),
         "mpow_plan_timing_reset": (c.c_int, [P]),
+        "mpow_plan_tile_table": (c.c_int, [P, P, c.c_int, c.c_int]),
+        "mpow_plan_autotune": (c.c_int, [P, c.c_char_p, c.c_uint32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -164,6 +169,24 @@ def mpow_plan_timing(plan: int, kernel: int):
 
 def mpow_plan_timing_reset(plan: int) -> None:
     _check(_load().mpow_plan_timing_reset(plan), "mpow_plan_timing_reset")
+
+
+def mpow_plan_tile_table(plan: int, table=None) -> list:
+    """Returns the batched kernel's tile table; replaces it first if given."""
+    buf = (ctypes.c_int * TILE_TABLE_LEN)()
+    if table is not None:
+        for i, v in enumerate(table):
+            buf[i] = int(v)
+        _check(_load().mpow_plan_tile_table(plan, ctypes.cast(buf, ctypes.c_void_p), TILE_TABLE_LEN, 1),
+               "mpow_plan_tile_table")
+    _check(_load().mpow_plan_tile_table(plan, ctypes.cast(buf, ctypes.c_void_p), TILE_TABLE_LEN, 0),
+           "mpow_plan_tile_table")
+    return [int(v) for v in buf]
+
+
+def mpow_plan_autotune(plan: int, cache_path: str | None = None, flags: int = 0) -> None:
+    _check(_load().mpow_plan_autotune(plan, cache_path.encode() if cache_path else None, int(flags)),
+           "mpow_plan_autotune")
 
 
 # ---------------------------------------------------------------- torch helpers

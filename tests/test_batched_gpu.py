@@ -212,3 +212,41 @@ def test_batched_invalid_arguments(plans):
     assert e.value.status == mpow.MPOW_ERR_INVALID
     mpow.mpow_run_batched(hb, 0, [], [], [], [], None, None)  # empty batch is fine
     torch.cuda.synchronize()
+
+
+def test_tile_shapes_bit_identical(plans):
+    hb, _ = plans
+    mats, ps = edge_batch(5)
+    pk = Packed(mats)
+    saved = mpow.mpow_plan_tile_table(hb)
+    results = []
+    for shape in range(4):
+        mpow.mpow_plan_tile_table(hb, [shape] * mpow.TILE_TABLE_LEN)
+        pk.out.fill_(float("nan"))
+        run_batch(hb, pk, ps)
+        results.append([pk.result(i) for i in range(len(ps))])
+    mpow.mpow_plan_tile_table(hb, saved)
+    for shape in range(1, 4):
+        for i in range(len(ps)):
+            assert np.array_equal(results[shape][i][0], results[0][i][0]), (shape, i)
+            assert results[shape][i][1] == results[0][i][1]
+
+
+def test_autotune_and_cache(plans, tmp_path):
+    hb, _ = plans
+    cache = str(tmp_path / "tune.txt")
+    print("  [gpu] mpow_plan_autotune", flush=True)
+    mpow.mpow_plan_autotune(hb, cache, mpow.MPOW_TUNE_FORCE)
+    table = mpow.mpow_plan_tile_table(hb)
+    assert all(0 <= t < 4 for t in table)
+    text = open(cache).read().splitlines()
+    assert text[0].startswith("mpow-tune ") and len(text) == 17
+    h2 = mpow.mpow_plan_create(0, 256, 16, mpow.MPOW_FP32, 0)
+    try:
+        mpow.mpow_plan_tile_table(h2, [1] * mpow.TILE_TABLE_LEN)
+        mpow.mpow_plan_autotune(h2, cache, 0)  # loads the cached table
+        assert mpow.mpow_plan_tile_table(h2)[1:] == table[1:]
+    finally:
+        mpow.mpow_plan_destroy(h2)
+    with pytest.raises(mpow.MpowError):
+        mpow.mpow_plan_tile_table(hb, [7] * mpow.TILE_TABLE_LEN)
