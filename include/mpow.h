@@ -45,7 +45,8 @@ typedef enum mpow_status {
     MPOW_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
     MPOW_ERR_NOMEM = 3,       /* device or pinned host allocation failed */
     MPOW_ERR_DEVICE = 4,      /* a HIP call failed; see mpow_last_device_error */
-    MPOW_ERR_BUDGET = 5       /* request can never fit the memory budget */
+    MPOW_ERR_BUDGET = 5,      /* request can never fit the memory budget */
+    MPOW_ERR_TIMEOUT = 6      /* a wait ended before the condition held */
 } mpow_status;
 
 /* Arithmetic of the matrix products.  Inputs and outputs are float32 in every
@@ -177,6 +178,97 @@ enum {
 mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, double *total_ms,
                              double *total_flop, const char **name);
 mpow_status mpow_plan_timing_reset(mpow_plan_t plan);
+
+/* ------------------------------------------------------------------------
+ * Request server (continuous batching).
+ *
+ * An engine thread owns a device-memory arena of hbm_budget bytes, n_streams
+ * HIP streams and a ragged-batch context.  Requests are independent powers
+ * (the same operation as mpow_run) of mixed n, p and mode:
+ *  - float32 requests with n <= 256 (and max_batch > 0) wait in one FIFO and
+ *    leave together, up to max_batch at a time, as one persistent batched
+ *    launch whenever no batch is running; requests arriving meanwhile join
+ *    the next batch.
+ *  - every other request is admitted in arrival order once its workspace
+ *    (mpow_workspace_bytes(n, 0, mode)) fits the unused part of the arena and
+ *    one of the streams has fewer than 2 requests in flight; it then runs on
+ *    that stream, its operands and partial powers staying in its arena
+ *    region, overlapping with the other streams and the batch.
+ * Results do not depend on what else runs: every request's kernels and their
+ * accumulation order depend only on (n, mode).
+ * ------------------------------------------------------------------------ */
+typedef struct mpow_srv *mpow_srv_t;
+
+typedef struct mpow_completion {
+    uint64_t id;
+    int32_t status;  /* MPOW_SUCCESS or MPOW_ERR_DEVICE */
+    int32_t route;   /* 0: own stream, 1: batched */
+    double t_submit; /* seconds since server creation (host steady clock) */
+    double t_start;  /* when the engine enqueued its work */
+    double t_end;    /* when the engine saw its completion event */
+} mpow_completion;
+
+typedef struct mpow_srv_stats_t {
+    uint64_t submitted, completed, rejected;
+    int32_t queued, in_flight;
+    size_t arena_capacity, arena_in_use, arena_peak;
+    int32_t last_device_error;
+    int32_t pad;
+} mpow_srv_stats_t;
+
+/* Creates a server on `device` for matrices up to max_n, with an arena of
+ * hbm_budget bytes (allocated here), n_streams streams (1..64) and batches of
+ * up to max_batch small requests (0: no batching).  flags must be 0.
+ * Errors: INVALID, DEVICE, NOMEM. */
+mpow_status mpow_srv_create(mpow_srv_t *srv, int device, int max_n, size_t hbm_budget,
+                            int n_streams, int max_batch, uint32_t flags);
+
+/* Queues A^p (device pointers as in mpow_run; A and out must stay valid and
+ * untouched until the request completes).  Never blocks on the device.
+ * *id (may be NULL) receives the request id.  Errors: INVALID (arguments,
+ * n > max_n, server stopping), BUDGET (its workspace exceeds the whole
+ * arena: it could never run). */
+mpow_status mpow_srv_submit(mpow_srv_t srv, const float *A, int n, int64_t p, int mode, float *out,
+                            double *log2_scale, uint64_t *id);
+
+/* Moves up to max completion records into out (oldest first); returns their
+ * number, or -1 for bad arguments. */
+int mpow_srv_poll(mpow_srv_t srv, mpow_completion *out, int max);
+
+/* Blocks until every submitted request has completed, or timeout_s passes
+ * (TIMEOUT). */
+mpow_status mpow_srv_wait_idle(mpow_srv_t srv, double timeout_s);
+
+mpow_status mpow_srv_stats(mpow_srv_t srv, mpow_srv_stats_t *stats);
+
+/* Stops accepting requests, lets the engine finish every queued and running
+ * one, then frees everything.  NULL is accepted. */
+mpow_status mpow_srv_destroy(mpow_srv_t srv);
+
+/* CPU-only run of the same admission and batching policy against a simulated
+ * executor (no device is touched): each stream runs its requests one after
+ * another at plain_flops, a batch takes launch_overhead_s plus its flops at
+ * batch_flops, a request costs launch_overhead_s plus 2 G(p) n^3 flops.
+ * reqs must be sorted by t_arrive.  results[i] receives the status (SUCCESS or
+ * BUDGET), route, stream and simulated admission/start/end times of request i;
+ * *peak_bytes the largest arena use.  Errors: INVALID; BUDGET if the policy
+ * ever exceeded the budget (a bug). */
+typedef struct mpow_sim_config {
+    size_t hbm_budget;
+    int32_t n_streams, depth, batch_cap, pad;
+    double plain_flops, batch_flops, launch_overhead_s;
+} mpow_sim_config;
+typedef struct mpow_sim_request {
+    double t_arrive;
+    int32_t n, mode;
+    int64_t p;
+} mpow_sim_request;
+typedef struct mpow_sim_result {
+    int32_t status, route, stream, pad;
+    double t_admit, t_start, t_end;
+} mpow_sim_result;
+mpow_status mpow_srv_simulate(const mpow_sim_config *cfg, const mpow_sim_request *reqs, int count,
+                              mpow_sim_result *results, size_t *peak_bytes);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,7 @@ using namespace mpow;
 
 namespace {
 
-constexpr int kBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
+constexpr int kBuckets = kTileBuckets;
 constexpr int kShapes = 4;                     // tile shape ids of the batched kernel
 
 struct DevGuard {
@@ -84,9 +84,9 @@ mpow_status mpow_plan_tile_table(mpow_plan_t plan, int *table, int len, int set)
     if (set) {
         for (int b = 0; b < kBuckets; ++b)
             if (table[b] < 0 || table[b] >= kShapes) return MPOW_ERR_INVALID;
-        for (int b = 0; b < kBuckets; ++b) plan->batch_cfg[b] = table[b];
+        for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = table[b];
     } else {
-        for (int b = 0; b < kBuckets; ++b) table[b] = plan->batch_cfg[b];
+        for (int b = 0; b < kBuckets; ++b) table[b] = plan->batch.cfg[b];
     }
     return MPOW_SUCCESS;
 }
@@ -100,24 +100,21 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
     const int bmax = plan->max_n < kBatchMaxN ? plan->max_n : kBatchMaxN;
     if (cache_path && !(flags & MPOW_TUNE_FORCE)) {
         int table[kBuckets];
-        for (int b = 0; b < kBuckets; ++b) table[b] = plan->batch_cfg[b];
+        for (int b = 0; b < kBuckets; ++b) table[b] = plan->batch.cfg[b];
         if (load_cache(cache_path, key, table)) {
-            for (int b = 0; b < kBuckets; ++b) plan->batch_cfg[b] = table[b];
+            for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = table[b];
             return MPOW_SUCCESS;
         }
     }
     hipError_t e;
-    if (plan->batch_pending) {
-        e = hipEventSynchronize(plan->batch_done);
-        if (e != hipSuccess) {
-            plan->last_error = (int)e;
-            return MPOW_ERR_DEVICE;
-        }
-        plan->batch_pending = false;
+    e = batch_wait_previous(&plan->batch);
+    if (e != hipSuccess) {
+        plan->last_error = (int)e;
+        return MPOW_ERR_DEVICE;
     }
 
-    const int count = plan->max_batch < 2 * plan->batch_workers ? plan->max_batch
-                                                                : 2 * plan->batch_workers;
+    const int count = plan->max_batch < 2 * plan->batch.workers ? plan->max_batch
+                                                                : 2 * plan->batch.workers;
     const size_t mat = (size_t)bmax * bmax;
     float *in = nullptr, *out = nullptr;
     hipStream_t s = nullptr;
@@ -145,17 +142,17 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         st = MPOW_ERR_DEVICE;
 
     BatchLaunch bl;
-    bl.desc = plan->batch_desc;
-    bl.scratch = plan->batch_scratch;
-    bl.slot_floats = plan->batch_slot_floats;
-    BatchHeader *hdr = (BatchHeader *)plan->batch_host;
+    bl.desc = plan->batch.desc;
+    bl.scratch = plan->batch.scratch;
+    bl.slot_floats = plan->batch.slot_floats;
+    BatchHeader *hdr = (BatchHeader *)plan->batch.host;
     BatchItem *items = (BatchItem *)(hdr + 1);
     const size_t bytes = sizeof(BatchHeader) + (size_t)count * sizeof(BatchItem);
 
     for (int b = 1; st == MPOW_SUCCESS && b * 16 <= bmax; ++b) {
         const int n = b * 16;
         float best = 1e30f;
-        int best_shape = plan->batch_cfg[b];
+        int best_shape = plan->batch.cfg[b];
         for (int shape = 0; shape < kShapes && st == MPOW_SUCCESS; ++shape) {
             float t_min = 1e30f;
             for (int rep = 0; rep < 4 && st == MPOW_SUCCESS; ++rep) {
@@ -170,9 +167,9 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                     items[i].cfg = shape;
                 }
                 float ms = 0.f;
-                if (hipMemcpyAsync(plan->batch_desc, plan->batch_host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+                if (hipMemcpyAsync(plan->batch.desc, plan->batch.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
                     hipEventRecord(e0, s) != hipSuccess ||
-                    launch_batched(bl, plan->batch_workers, s) != hipSuccess ||
+                    launch_batched(bl, plan->batch.workers, s) != hipSuccess ||
                     hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                     st = MPOW_ERR_DEVICE;
@@ -185,7 +182,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                 best_shape = shape;
             }
         }
-        if (st == MPOW_SUCCESS) plan->batch_cfg[b] = best_shape;
+        if (st == MPOW_SUCCESS) plan->batch.cfg[b] = best_shape;
     }
     if (st != MPOW_SUCCESS) plan->last_error = (int)hipGetLastError();
     if (e0) (void)hipEventDestroy(e0);
@@ -193,7 +190,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
     if (s) (void)hipStreamDestroy(s);
     (void)hipFree(in);
     (void)hipFree(out);
-    if (st == MPOW_SUCCESS && cache_path) (void)save_cache(cache_path, key, plan->batch_cfg, bmax);
+    if (st == MPOW_SUCCESS && cache_path) (void)save_cache(cache_path, key, plan->batch.cfg, bmax);
     return st;
 }
 

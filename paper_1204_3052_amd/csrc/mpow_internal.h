@@ -5,32 +5,69 @@
 
 #include <cstddef>
 #include <cstdint>
-#include <string>
 #include <vector>
 
 #include "../../include/mpow.h"
 
 namespace mpow {
 
-// Workspace layout of one plan (all device memory, allocated at plan creation).
-//  buf[0], buf[1]  ping-pong running matrices, max_n^2 floats each
+// ---------------------------------------------------------------- workspace
+
+// Device memory one power needs (plan-owned, or carved from a server arena).
+//  buf[0], buf[1]   ping-pong running matrices, n^2 floats each
 //  part[0], part[1] per-tile partial sums of squares of buf[0] / buf[1]
 //  partA            per-block partial sums of squares of the input A
 //  escale           escale[k] = floor(log2 ||C_k||_F) of the k-th product's
 //                   output (C_0 = A), written by the kernel that consumes C_k
+//  sx, sa           split modes: 16-bit hi/lo of the running matrix and of A
+//                   (row-major hi, lo, then transposed hi, lo), ld x ld each
 struct Workspace {
-    // split modes: hi/lo of the running matrix (row-major, transposed) and of A
-    void *sx[4] = {nullptr, nullptr, nullptr, nullptr};
-    void *sa[4] = {nullptr, nullptr, nullptr, nullptr};
     float *buf[2] = {nullptr, nullptr};
     double *part[2] = {nullptr, nullptr};
     double *partA = nullptr;
     int *escale = nullptr;
-    size_t part_cap = 0;   // doubles in each part[] array
-    size_t partA_cap = 0;  // doubles in partA
+    void *sx[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *sa[4] = {nullptr, nullptr, nullptr, nullptr};
+    int max_n = 0;
+    int mode = MPOW_FP32;
 };
 
-// How one product kernel is launched.
+size_t round_up(size_t x, size_t a);
+// Bytes of one workspace for matrices up to max_n in `mode` (256-aligned).
+size_t workspace_bytes(int max_n, int mode);
+// Lays a workspace out over [base, base + workspace_bytes(max_n, mode)).
+void workspace_carve(char *base, int max_n, int mode, Workspace *ws);
+
+// ---------------------------------------------------------------- timing
+
+struct TimingRecord {
+    int kernel;
+    double flop;
+    hipEvent_t start, stop;
+};
+
+// Optional HIP-event timing of product launches (MPOW_FLAG_TIMING).
+struct TimingSink {
+    std::vector<hipEvent_t> free_events;
+    std::vector<TimingRecord> pending;
+    int64_t launches[MPOW_KERNEL_COUNT] = {};
+    double ms[MPOW_KERNEL_COUNT] = {};
+    double flop[MPOW_KERNEL_COUNT] = {};
+    hipError_t start(int kernel, double flop, hipStream_t s, TimingRecord *rec);
+    hipError_t stop(TimingRecord *rec, hipStream_t s);
+    hipError_t collect();  // waits for pending records and accumulates them
+    void reset();
+    void destroy();
+};
+
+// Enqueues A^p on stream s using workspace ws (ws.max_n >= n, ws.mode = mode).
+// Arguments must already be validated.  Returns the first HIP error.
+hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
+                         double *log2_scale, hipStream_t s, TimingSink *timing);
+
+// ---------------------------------------------------------------- kernels
+
+// How one float32 product kernel is launched.
 struct GemmLaunch {
     const float *X;          // left operand (scaled by 2^-eX on load)
     const double *partX;     // partial sums of squares of X
@@ -71,8 +108,24 @@ int gemm_split_tiles(int kernel, int n);
 const char *gemm_split_name(int kernel);
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s);
 
-// Ragged batch: descriptors the host fills (sorted by work), a header with
-// the claim counter, and per-worker scratch.
+// Float32 product kernel variants (index = MPOW_KERNEL_* id).
+int gemm_pick(int n);                       // kernel id used for size n
+int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
+const char *gemm_name(int kernel);
+hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s);
+
+// Scale and bookkeeping kernels.
+int norm_blocks(int n);
+hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s);
+hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s);
+hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
+                         const int *escale, int64_t p, float *out, double *log2_scale,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------- ragged batch
+
+// Descriptors the host fills (sorted by work), after a header holding the
+// claim counter; per-worker scratch.
 struct BatchHeader {
     int counter;  // next descriptor to claim; the host copy resets it to 0
     int count;
@@ -92,33 +145,48 @@ struct BatchLaunch {
     int64_t slot_floats;  // floats per scratch buffer (max batched n squared)
 };
 constexpr int kBatchMaxN = 256;
+constexpr int kTileBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
 int batched_cfg_for(int n);
 int batched_occupancy();  // resident workers per CU
 hipError_t launch_batched(const BatchLaunch &b, int grid, hipStream_t s);
 
-// Product kernel variants (index = MPOW_KERNEL_* id).
-int gemm_pick(int n);                       // kernel id used for size n
-int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
-const char *gemm_name(int kernel);
-hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s);
+// Everything one stream of ragged batches needs: device descriptors and
+// scratch, a pinned host copy of the descriptors, the tile table and an
+// optional captured graph (copy + launch).  One batch in flight at a time.
+struct BatchContext {
+    void *desc = nullptr;
+    void *host = nullptr;
+    float *scratch = nullptr;
+    int64_t slot_floats = 0;
+    int workers = 0;
+    int max_batch = 0;
+    int cfg[kTileBuckets] = {};
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_count = -1;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+size_t batch_desc_bytes(int max_batch);
+// Device bytes (descriptors + scratch) for a context.
+size_t batch_device_bytes(int max_batch, int bmax, int workers);
+// Sets up a context over [dev, dev + batch_device_bytes(...)); creates the
+// pinned buffer, capture stream and event.
+hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax, int workers);
+void batch_context_release(BatchContext *bc);
+// Waits until the previous batch has consumed the pinned descriptors.
+hipError_t batch_wait_previous(BatchContext *bc);
+// Fills descriptors in longest-work-first order and enqueues the batch on s
+// (through the captured graph when use_graph).  scale may be null, or hold a
+// per-item pointer that may itself be null.
+hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, const int *n,
+                         const int64_t *p, float *const *out, double *const *scale,
+                         hipStream_t s, bool use_graph);
 
-// Scale and bookkeeping kernels.
-int norm_blocks(int n);
-hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s);
-hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s);
-hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
-                         const int *escale, int64_t p, int steps, float *out,
-                         double *log2_scale, hipStream_t s);
+// Resident workers of the batched kernel on `device` (CUs x occupancy).
+int batch_workers_for(int device);
 
 }  // namespace mpow
-
-using mpow::kBatchMaxN;
-
-struct TimingRecord {
-    int kernel;
-    double flop;
-    hipEvent_t start, stop;
-};
 
 struct mpow_plan {
     int device = 0;
@@ -127,23 +195,8 @@ struct mpow_plan {
     int mode = 0;
     uint32_t flags = 0;
     int last_error = 0;
+    char *base = nullptr;  // the plan's single device allocation
     mpow::Workspace ws;
-    // timing (MPOW_FLAG_TIMING)
-    std::vector<hipEvent_t> free_events;
-    std::vector<TimingRecord> pending;
-    int64_t launches[MPOW_KERNEL_COUNT] = {};
-    double ms[MPOW_KERNEL_COUNT] = {};
-    double flop[MPOW_KERNEL_COUNT] = {};
-    // ragged batch (max_batch > 0)
-    void *batch_desc = nullptr;    // device: BatchHeader + max_batch items
-    void *batch_host = nullptr;    // pinned host copy the graph's memcpy reads
-    float *batch_scratch = nullptr;
-    int64_t batch_slot_floats = 0;
-    int batch_workers = 0;
-    int batch_cfg[kBatchMaxN / 16 + 1] = {};  // tile shape per n bucket ((n+15)/16)
-    hipStream_t capture_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_count = -1;
-    hipEvent_t batch_done = nullptr;
-    bool batch_pending = false;
+    mpow::TimingSink timing;
+    mpow::BatchContext batch;
 };

@@ -1,0 +1,359 @@
+// Host runtime: workspace layout, the enqueueing of one power (the product
+// schedule of the paper's section 4.3 method), ragged-batch contexts and
+// HIP-event timing.  Shared by plans and by the request server.
+#include <algorithm>
+#include <vector>
+
+#include "mpow_internal.h"
+
+namespace mpow {
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+namespace {
+
+struct Layout {
+    size_t buf, part, partA, escale, split, total;
+};
+
+Layout layout_for(int max_n, int mode) {
+    Layout z;
+    const size_t n = (size_t)max_n;
+    const size_t t32 = (n + 31) / 32;  // the smallest product tile is 32 x 32
+    z.buf = round_up(n * n * sizeof(float), 256);
+    z.part = round_up(t32 * t32 * sizeof(double), 256);
+    z.partA = round_up(512 * sizeof(double), 256);
+    z.escale = round_up((MPOW_MAX_STEPS + 2) * sizeof(int), 256);
+    const size_t ld = (size_t)split_ld(max_n);
+    z.split = mode == MPOW_FP32 ? 0 : round_up(ld * ld * 2, 256);
+    z.total = 2 * z.buf + 2 * z.part + z.partA + z.escale + 8 * z.split;
+    return z;
+}
+
+}  // namespace
+
+size_t workspace_bytes(int max_n, int mode) { return layout_for(max_n, mode).total; }
+
+void workspace_carve(char *base, int max_n, int mode, Workspace *ws) {
+    const Layout z = layout_for(max_n, mode);
+    char *q = base;
+    ws->buf[0] = (float *)q; q += z.buf;
+    ws->buf[1] = (float *)q; q += z.buf;
+    ws->part[0] = (double *)q; q += z.part;
+    ws->part[1] = (double *)q; q += z.part;
+    ws->partA = (double *)q; q += z.partA;
+    ws->escale = (int *)q; q += z.escale;
+    for (int k = 0; k < 4; ++k) {
+        ws->sx[k] = z.split ? (void *)q : nullptr; q += z.split;
+        ws->sa[k] = z.split ? (void *)q : nullptr; q += z.split;
+    }
+    ws->max_n = max_n;
+    ws->mode = mode;
+}
+
+// ---------------------------------------------------------------- timing
+
+hipError_t TimingSink::start(int kernel, double f, hipStream_t s, TimingRecord *rec) {
+    rec->kernel = kernel;
+    rec->flop = f;
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+        if (!free_events.empty()) {
+            ev[i] = free_events.back();
+            free_events.pop_back();
+        } else {
+            const hipError_t e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) return e;
+        }
+    }
+    rec->start = ev[0];
+    rec->stop = ev[1];
+    return hipEventRecord(rec->start, s);
+}
+
+hipError_t TimingSink::stop(TimingRecord *rec, hipStream_t s) {
+    const hipError_t e = hipEventRecord(rec->stop, s);
+    if (e == hipSuccess) pending.push_back(*rec);
+    return e;
+}
+
+hipError_t TimingSink::collect() {
+    for (auto &r : pending) {
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return e;
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, r.start, r.stop);
+        if (e != hipSuccess) return e;
+        launches[r.kernel] += 1;
+        ms[r.kernel] += t;
+        flop[r.kernel] += r.flop;
+        free_events.push_back(r.start);
+        free_events.push_back(r.stop);
+    }
+    pending.clear();
+    return hipSuccess;
+}
+
+void TimingSink::reset() {
+    for (int k = 0; k < MPOW_KERNEL_COUNT; ++k) {
+        launches[k] = 0;
+        ms[k] = 0.0;
+        flop[k] = 0.0;
+    }
+}
+
+void TimingSink::destroy() {
+    for (auto &r : pending) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    pending.clear();
+    for (auto e : free_events) (void)hipEventDestroy(e);
+    free_events.clear();
+}
+
+// ---------------------------------------------------------------- one power
+
+namespace {
+
+int schedule_of(int64_t p, uint8_t *ops) {
+    if (p < 2) return 0;
+    const int top = 63 - __builtin_clzll((unsigned long long)p);
+    int k = 0;
+    for (int bit = top - 1; bit >= 0; --bit) {
+        ops[k++] = 0;
+        if ((p >> bit) & 1) ops[k++] = 1;
+    }
+    return k;
+}
+
+#define MPOW_TRY(expr)                          \
+    do {                                        \
+        const hipError_t e_ = (expr);           \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+// Float32 products: step k computes C_k = (2^-e X)(2^-e' Y) from the
+// partial sums of its operands; X = C_{k-1} (C_0 = A), Y = X (square) or A.
+hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const uint8_t *ops,
+                    int G, int nbA, float *out, double *log2_scale, hipStream_t s,
+                    TimingSink *timing) {
+    const int kernel = gemm_pick(n);
+    const int tiles = gemm_tiles(kernel, n);
+    const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+    const float *X = A;
+    const double *partX = ws.partA;
+    int nPartX = nbA;
+    for (int k = 1; k <= G; ++k) {
+        GemmLaunch g;
+        g.X = X;
+        g.partX = partX;
+        g.nPartX = nPartX;
+        if (ops[k - 1] == 0) {
+            g.Y = X;
+            g.partY = partX;
+            g.nPartY = nPartX;
+        } else {
+            g.Y = A;
+            g.partY = ws.partA;
+            g.nPartY = nbA;
+        }
+        g.C = ws.buf[k & 1];
+        g.partC = ws.part[k & 1];
+        g.eSlot = ws.escale + (k - 1);
+        g.n = n;
+        TimingRecord rec{};
+        if (timing) MPOW_TRY(timing->start(kernel, flop, s, &rec));
+        MPOW_TRY(gemm_launch(kernel, g, vec4, s));
+        if (timing) MPOW_TRY(timing->stop(&rec, s));
+        X = g.C;
+        partX = g.partC;
+        nPartX = tiles;
+    }
+    return launch_finish(X, n, partX, nPartX, ws.escale, p, out, log2_scale, s);
+}
+
+// Split-precision products: A is split once (both layouts); after every
+// product but the last, the float32 result is split again with its own scale.
+hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, const uint8_t *ops,
+                     int G, int nbA, float *out, double *log2_scale, hipStream_t s,
+                     TimingSink *timing) {
+    const int mode = ws.mode;
+    const int ld = split_ld(n);
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+    const int kernel = gemm_split_pick(mode, n);
+    const int tiles = gemm_split_tiles(kernel, n);
+
+    SplitLaunch sl;
+    sl.X = A;
+    sl.part = ws.partA;
+    sl.nPart = nbA;
+    sl.n = n;
+    sl.ld = ld;
+    sl.hi = ws.sa[0];
+    sl.lo = ws.sa[1];
+    sl.hiT = ws.sa[2];
+    sl.loT = ws.sa[3];
+    sl.eSlot = ws.escale;
+    MPOW_TRY(launch_split(mode, sl, s));
+
+    for (int k = 1; k <= G; ++k) {
+        void *const *xs = (k == 1) ? ws.sa : ws.sx;
+        void *const *ys = (ops[k - 1] == 0) ? xs : ws.sa;
+        SplitGemmLaunch g;
+        g.xh = xs[0];
+        g.xl = xs[1];
+        g.yh = ys[2];
+        g.yl = ys[3];
+        g.C = ws.buf[k & 1];
+        g.partC = ws.part[k & 1];
+        g.n = n;
+        g.ld = ld;
+        TimingRecord rec{};
+        if (timing) MPOW_TRY(timing->start(kernel, flop, s, &rec));
+        MPOW_TRY(gemm_split_launch(kernel, g, s));
+        if (timing) MPOW_TRY(timing->stop(&rec, s));
+        if (k < G) {
+            sl.X = g.C;
+            sl.part = g.partC;
+            sl.nPart = tiles;
+            sl.hi = ws.sx[0];
+            sl.lo = ws.sx[1];
+            sl.hiT = ws.sx[2];
+            sl.loT = ws.sx[3];
+            sl.eSlot = ws.escale + k;
+            MPOW_TRY(launch_split(mode, sl, s));
+        }
+    }
+    return launch_finish(ws.buf[G & 1], n, ws.part[G & 1], tiles, ws.escale, p, out, log2_scale, s);
+}
+
+}  // namespace
+
+hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
+                         double *log2_scale, hipStream_t s, TimingSink *timing) {
+    if (p == 0) return launch_identity(out, n, log2_scale, s);
+    const int nbA = norm_blocks(n);
+    MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
+    uint8_t ops[MPOW_MAX_STEPS];
+    const int G = schedule_of(p, ops);
+    if (G == 0) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
+    if (ws.mode != MPOW_FP32) return run_split(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
+    return run_fp32(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
+}
+
+// ---------------------------------------------------------------- ragged batch
+
+size_t batch_desc_bytes(int max_batch) {
+    return sizeof(BatchHeader) + (size_t)max_batch * sizeof(BatchItem);
+}
+
+size_t batch_device_bytes(int max_batch, int bmax, int workers) {
+    return round_up(batch_desc_bytes(max_batch), 256) +
+           round_up((size_t)workers * 2 * (size_t)bmax * bmax * sizeof(float), 256);
+}
+
+int batch_workers_for(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    const int w = cus * batched_occupancy();
+    return w < 1 ? 1 : w;
+}
+
+hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax, int workers) {
+    bc->desc = dev;
+    bc->scratch = (float *)(dev + round_up(batch_desc_bytes(max_batch), 256));
+    bc->slot_floats = (int64_t)bmax * bmax;
+    bc->workers = workers;
+    bc->max_batch = max_batch;
+    for (int b = 0; b < kTileBuckets; ++b) bc->cfg[b] = batched_cfg_for(b * 16);
+    MPOW_TRY(hipHostMalloc(&bc->host, batch_desc_bytes(max_batch), hipHostMallocDefault));
+    MPOW_TRY(hipStreamCreateWithFlags(&bc->capture_stream, hipStreamNonBlocking));
+    MPOW_TRY(hipEventCreateWithFlags(&bc->done, hipEventDisableTiming));
+    return hipSuccess;
+}
+
+void batch_context_release(BatchContext *bc) {
+    if (bc->graph_exec) (void)hipGraphExecDestroy(bc->graph_exec);
+    if (bc->done) (void)hipEventDestroy(bc->done);
+    if (bc->capture_stream) (void)hipStreamDestroy(bc->capture_stream);
+    if (bc->host) (void)hipHostFree(bc->host);
+    *bc = BatchContext();
+}
+
+hipError_t batch_wait_previous(BatchContext *bc) {
+    if (!bc->pending) return hipSuccess;
+    MPOW_TRY(hipEventSynchronize(bc->done));
+    bc->pending = false;
+    return hipSuccess;
+}
+
+hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, const int *n,
+                         const int64_t *p, float *const *out, double *const *scale,
+                         hipStream_t s, bool use_graph) {
+    MPOW_TRY(batch_wait_previous(bc));
+    // Longest work first: estimated work (G(p) + 1) n^3, ties by input order.
+    std::vector<int> order(count);
+    std::vector<double> work(count);
+    uint8_t ops[MPOW_MAX_STEPS];
+    for (int i = 0; i < count; ++i) {
+        order[i] = i;
+        const double nn = (double)n[i];
+        work[i] = (double)(schedule_of(p[i], ops) + 1) * nn * nn * nn;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    BatchHeader *hdr = (BatchHeader *)bc->host;
+    hdr->counter = 0;
+    hdr->count = count;
+    hdr->pad[0] = hdr->pad[1] = 0;
+    BatchItem *items = (BatchItem *)(hdr + 1);
+    for (int k = 0; k < count; ++k) {
+        const int i = order[k];
+        items[k].A = A[i];
+        items[k].out = out[i];
+        items[k].scale = scale ? scale[i] : nullptr;
+        items[k].p = p[i];
+        items[k].n = n[i];
+        items[k].cfg = bc->cfg[(n[i] + 15) / 16];
+    }
+    BatchLaunch bl;
+    bl.desc = bc->desc;
+    bl.scratch = bc->scratch;
+    bl.slot_floats = bc->slot_floats;
+    if (use_graph) {
+        if (!bc->graph_exec || bc->graph_count != count) {
+            if (bc->graph_exec) {
+                (void)hipGraphExecDestroy(bc->graph_exec);
+                bc->graph_exec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            MPOW_TRY(hipStreamBeginCapture(bc->capture_stream, hipStreamCaptureModeRelaxed));
+            const hipError_t e1 = hipMemcpyAsync(bc->desc, bc->host, batch_desc_bytes(count),
+                                                 hipMemcpyHostToDevice, bc->capture_stream);
+            const hipError_t e2 = launch_batched(bl, bc->workers, bc->capture_stream);
+            const hipError_t e3 = hipStreamEndCapture(bc->capture_stream, &graph);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+            }
+            const hipError_t e4 = hipGraphInstantiate(&bc->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e4 != hipSuccess) {
+                bc->graph_exec = nullptr;
+                return e4;
+            }
+            bc->graph_count = count;
+        }
+        MPOW_TRY(hipGraphLaunch(bc->graph_exec, s));
+    } else {
+        MPOW_TRY(hipMemcpyAsync(bc->desc, bc->host, batch_desc_bytes(count), hipMemcpyHostToDevice, s));
+        MPOW_TRY(launch_batched(bl, bc->workers, s));
+    }
+    MPOW_TRY(hipEventRecord(bc->done, s));
+    bc->pending = true;
+    return hipSuccess;
+}
+
+}  // namespace mpow

@@ -131,9 +131,8 @@ hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s)
 }
 
 hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
-                         const int *escale, int64_t p, int steps, float *out,
-                         double *log2_scale, hipStream_t s) {
-    (void)steps;
+                         const int *escale, int64_t p, float *out, double *log2_scale,
+                         hipStream_t s) {
     hipLaunchKernelGGL(finish_kernel, dim3(grid_for((int64_t)n * n, 512)), dim3(kNT), 0, s, C, n,
                        partC, nPartC, escale, p, out, log2_scale);
     return hipGetLastError();

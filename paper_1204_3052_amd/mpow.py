@@ -20,6 +20,7 @@ MPOW_ERR_UNSUPPORTED = 2
 MPOW_ERR_NOMEM = 3
 MPOW_ERR_DEVICE = 4
 MPOW_ERR_BUDGET = 5
+MPOW_ERR_TIMEOUT = 6
 
 MPOW_FP32 = 0
 MPOW_FP16X3 = 1
@@ -44,9 +45,40 @@ EXPORTS = (
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_batched",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
     "mpow_plan_tile_table", "mpow_plan_autotune",
+    "mpow_srv_create", "mpow_srv_submit", "mpow_srv_poll", "mpow_srv_wait_idle", "mpow_srv_stats",
+    "mpow_srv_destroy", "mpow_srv_simulate",
 )
 
 _lib = None
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("route", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_end", ctypes.c_double)]
+
+
+class SrvStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("queued", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+                ("arena_capacity", ctypes.c_size_t), ("arena_in_use", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t), ("last_device_error", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SimConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("n_streams", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("batch_cap", ctypes.c_int32), ("pad", ctypes.c_int32), ("plain_flops", ctypes.c_double),
+                ("batch_flops", ctypes.c_double), ("launch_overhead_s", ctypes.c_double)]
+
+
+class SimRequest(ctypes.Structure):
+    _fields_ = [("t_arrive", ctypes.c_double), ("n", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("p", ctypes.c_int64)]
+
+
+class SimResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("route", ctypes.c_int32), ("stream", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_end", ctypes.c_double)]
 
 
 class MpowError(RuntimeError):
@@ -86,6 +118,14 @@ def _load():
         "mpow_plan_timing_reset": (c.c_int, [P]),
         "mpow_plan_tile_table": (c.c_int, [P, P, c.c_int, c.c_int]),
         "mpow_plan_autotune": (c.c_int, [P, c.c_char_p, c.c_uint32]),
+        "mpow_srv_create": (c.c_int, [c.POINTER(P), c.c_int, c.c_int, c.c_size_t, c.c_int, c.c_int, c.c_uint32]),
+        "mpow_srv_submit": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_int, P, P, c.POINTER(c.c_uint64)]),
+        "mpow_srv_poll": (c.c_int, [P, c.POINTER(Completion), c.c_int]),
+        "mpow_srv_wait_idle": (c.c_int, [P, c.c_double]),
+        "mpow_srv_stats": (c.c_int, [P, c.POINTER(SrvStats)]),
+        "mpow_srv_destroy": (c.c_int, [P]),
+        "mpow_srv_simulate": (c.c_int, [c.POINTER(SimConfig), c.POINTER(SimRequest), c.c_int,
+                                        c.POINTER(SimResult), c.POINTER(c.c_size_t)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -187,6 +227,68 @@ def mpow_plan_tile_table(plan: int, table=None) -> list:
 def mpow_plan_autotune(plan: int, cache_path: str | None = None, flags: int = 0) -> None:
     _check(_load().mpow_plan_autotune(plan, cache_path.encode() if cache_path else None, int(flags)),
            "mpow_plan_autotune")
+
+
+def mpow_srv_create(device: int, max_n: int, hbm_budget: int, n_streams: int = 4,
+                    max_batch: int = 1024, flags: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(_load().mpow_srv_create(ctypes.byref(h), int(device), int(max_n), int(hbm_budget),
+                                   int(n_streams), int(max_batch), int(flags)), "mpow_srv_create")
+    return h.value
+
+
+def mpow_srv_submit(srv: int, A: int, n: int, p: int, mode: int, out: int,
+                    log2_scale: int | None = None) -> int:
+    rid = ctypes.c_uint64()
+    _check(_load().mpow_srv_submit(srv, A, int(n), int(p), int(mode), out, log2_scale or None,
+                                   ctypes.byref(rid)), "mpow_srv_submit")
+    return rid.value
+
+
+def mpow_srv_poll(srv: int, max_items: int = 4096) -> list:
+    buf = (Completion * max_items)()
+    k = _load().mpow_srv_poll(srv, buf, max_items)
+    if k < 0:
+        raise MpowError(MPOW_ERR_INVALID, "mpow_srv_poll")
+    return [{"id": buf[i].id, "status": buf[i].status, "route": buf[i].route,
+             "t_submit": buf[i].t_submit, "t_start": buf[i].t_start, "t_end": buf[i].t_end}
+            for i in range(k)]
+
+
+def mpow_srv_wait_idle(srv: int, timeout_s: float = 60.0) -> None:
+    _check(_load().mpow_srv_wait_idle(srv, float(timeout_s)), "mpow_srv_wait_idle")
+
+
+def mpow_srv_stats(srv: int) -> dict:
+    st = SrvStats()
+    _check(_load().mpow_srv_stats(srv, ctypes.byref(st)), "mpow_srv_stats")
+    return {f: getattr(st, f) for f, _ in SrvStats._fields_ if f != "pad"}
+
+
+def mpow_srv_destroy(srv: int) -> None:
+    _check(_load().mpow_srv_destroy(srv), "mpow_srv_destroy")
+
+
+def mpow_srv_simulate(requests, hbm_budget: int, n_streams: int = 4, depth: int = 2,
+                      batch_cap: int = 1024, plain_flops: float = 1e14, batch_flops: float = 5e13,
+                      launch_overhead_s: float = 1e-5):
+    """requests: sequence of (t_arrive, n, p, mode), sorted by t_arrive.
+    Returns (list of result dicts, peak arena bytes)."""
+    count = len(requests)
+    cfg = SimConfig(hbm_budget=int(hbm_budget), n_streams=n_streams, depth=depth, batch_cap=batch_cap,
+                    pad=0, plain_flops=plain_flops, batch_flops=batch_flops,
+                    launch_overhead_s=launch_overhead_s)
+    reqs = (SimRequest * max(count, 1))()
+    for i, (t, n, p, mode) in enumerate(requests):
+        reqs[i] = SimRequest(float(t), int(n), int(mode), int(p))
+    res = (SimResult * max(count, 1))()
+    peak = ctypes.c_size_t()
+    _check(_load().mpow_srv_simulate(ctypes.byref(cfg), reqs, count, res, ctypes.byref(peak)),
+           "mpow_srv_simulate")
+    out = [{"status": res[i].status, "route": res[i].route, "stream": res[i].stream,
+            "t_admit": res[i].t_admit, "t_start": res[i].t_start, "t_end": res[i].t_end}
+           for i in range(count)]
+    return out, peak.value
 
 
 # ---------------------------------------------------------------- torch helpers
