@@ -208,15 +208,132 @@ def batched_workload(args):
     return 0
 
 
+def serving_workload(args):
+    """Open-loop request serving: Poisson arrivals at 2000 req/s, N
+    log-uniform on multiples of 16 in [32, 2048], p log-uniform in [2, 2^20],
+    half FP32 and half BF16X3, N(0,1)/sqrt(N) entries (one input matrix per
+    size, reused).  Reports p50/p99 latency (submit to completion seen by the
+    engine) beside throughput, and errors of a sample against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1204_3052_amd import inputs, mpow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rate = 2000.0
+    t_arr, ns, ps, split = inputs.poisson_trace(rate, args.duration, 5)
+    modes = np.where(split, mpow.MPOW_BF16X3, mpow.MPOW_FP32)
+    count = len(t_arr)
+    pool = {int(n): torch.from_numpy(inputs.gaussian(int(n), 9000 + int(n))).to(dev) for n in np.unique(ns)}
+    slots = 256
+    out = torch.empty((slots, 2048 * 2048), dtype=torch.float32, device=dev)
+    scale = torch.zeros(slots, dtype=torch.float64, device=dev)
+    # a stratified sample (by size) kept in its own buffers for the error check
+    rng = np.random.default_rng(0)
+    small_idx = np.flatnonzero(ns <= 512)
+    sample = set(int(i) for i in rng.choice(small_idx, min(24, len(small_idx)), replace=False))
+    samp_out = {i: torch.empty((int(ns[i]), int(ns[i])), device=dev) for i in sample}
+    samp_scale = torch.zeros(count, dtype=torch.float64, device=dev)
+    budget = 16 << 30
+    srv = mpow.mpow_srv_create(0, 2048, budget, n_streams=4, max_batch=1024)
+    torch.cuda.synchronize(dev)
+
+    # warm-up: every mode and route once
+    for n in (min(pool), max(pool)):
+        for m in (mpow.MPOW_FP32, mpow.MPOW_BF16X3):
+            mpow.mpow_srv_submit(srv, pool[n].data_ptr(), n, 17, m, out[0].data_ptr(), scale[0:1].data_ptr())
+            mpow.mpow_srv_wait_idle(srv, 60.0)
+    mpow.mpow_srv_poll(srv)
+
+    free = list(range(1, slots))
+    owner = {}
+    lat = np.full(count, np.nan)
+    t_sub = np.full(count, np.nan)
+    t_end = np.full(count, np.nan)
+    route = np.zeros(count, np.int32)
+    backpressure = 0
+
+    def drain():
+        for c in mpow.mpow_srv_poll(srv):
+            i, slot = owner.pop(c["id"])
+            if slot is not None:
+                free.append(slot)
+            lat[i] = c["t_end"] - c["t_submit"]
+            t_sub[i], t_end[i], route[i] = c["t_submit"], c["t_end"], c["route"]
+            if c["status"] != 0:
+                raise RuntimeError(f"request {i} failed with status {c['status']}")
+
+    t0 = time.perf_counter()
+    for i in range(count):
+        target = t0 + float(t_arr[i])
+        while True:
+            drain()
+            dt = target - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 2e-4))
+        n, p, m = int(ns[i]), int(ps[i]), int(modes[i])
+        if i in sample:
+            slot, o, sp = None, samp_out[i].data_ptr(), samp_scale[i:i + 1].data_ptr()
+        else:
+            while not free:
+                backpressure += 1
+                drain()
+                time.sleep(5e-5)
+            slot = free.pop()
+            o, sp = out[slot].data_ptr(), scale[slot:slot + 1].data_ptr()
+        rid = mpow.mpow_srv_submit(srv, pool[n].data_ptr(), n, p, m, o, sp)
+        owner[rid] = (i, slot)
+    mpow.mpow_srv_wait_idle(srv, 600.0)
+    drain()
+    wall = time.perf_counter() - t0
+    stats = mpow.mpow_srv_stats(srv)
+    mpow.mpow_srv_destroy(srv)
+
+    flop = np.array([gemm_count(int(p)) * 2.0 * float(n) ** 3 for n, p in zip(ns, ps)])
+    span = float(np.nanmax(t_end) - np.nanmin(t_sub))
+
+    def pct(x, q):
+        x = x[np.isfinite(x)]
+        return round(float(np.percentile(x, q)) * 1e3, 3) if len(x) else None
+
+    by = {}
+    for name, mask in (("fp32", modes == mpow.MPOW_FP32), ("bf16x3", modes == mpow.MPOW_BF16X3),
+                       ("batched_route", route == 1), ("n_ge_1024", ns >= 1024)):
+        by[name] = {"count": int(mask.sum()), "p50_ms": pct(lat[mask], 50), "p99_ms": pct(lat[mask], 99)}
+    errs = []
+    for i in sorted(sample):
+        A = pool[int(ns[i])].cpu().numpy()
+        ref = oracle.mpow_binary(A, int(ps[i]))
+        errs.append({"n": int(ns[i]), "p": int(ps[i]), "mode": "bf16x3" if modes[i] else "fp32",
+                     "rel_err": float(f"{oracle.rel_err(samp_out[i].cpu().numpy(), float(samp_scale[i].item()), *ref):.3e}")})
+    print(json.dumps({
+        "workload": f"serving: Poisson {rate:.0f} req/s for {args.duration:.0f} s, N log-uniform [32,2048] "
+                    "step 16, p log-uniform [2,2^20], 50% FP32 / 50% BF16X3",
+        "requests": count, "completed": int(np.isfinite(lat).sum()),
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": round(float(np.nanmean(lat)) * 1e3, 3)},
+        "by_class": by,
+        "throughput_gflops": round(float(flop.sum()) / span / 1e9, 1),
+        "offered_gflops": round(float(flop.sum()) / args.duration / 1e9, 1),
+        "span_s": round(span, 3), "wall_s": round(wall, 3), "backpressure_waits": backpressure,
+        "arena_peak_bytes": int(stats["arena_peak"]), "arena_budget_bytes": budget,
+        "sample_errors": errs}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched", "serving"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
                          "at N=4096, p in {64, 1000}, with errors against the oracle")
+    ap.add_argument("--duration", type=float, default=60.0,
+                    help="serving workload: seconds of Poisson arrivals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -242,6 +359,8 @@ def main():
         return split_workload(args)
     if args.workload == "batched":
         return batched_workload(args)
+    if args.workload == "serving":
+        return serving_workload(args)
 
     import numpy as np
     import torch
