@@ -18,10 +18,10 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_f32_kernel(GemmLaunch g) {
     __shared__ double red[NT];
 
     const int n = g.n;
-    const int tilesN = (n + BN - 1) / BN;
-    const int tile = blockIdx.x;
-    const int m0 = (tile / tilesN) * BM;
-    const int n0 = (tile % tilesN) * BN;
+    int tm, tn;
+    tile_of_block(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
 
     // Scales of both operands from their partial sums of squares.
     const int eX = exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red));
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_f32_kernel(GemmLaunch g) {
 
     const double ss = f32_tile<BM, BN, WM, WN, VEC>(g.X, pow2_neg(eX), g.Y, pow2_neg(eY), g.C, n,
                                                     m0, n0, As, Bs, red);
-    if (threadIdx.x == 0) g.partC[tile] = ss;
+    if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
 struct Variant {

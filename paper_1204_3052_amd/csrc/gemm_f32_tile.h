@@ -156,25 +156,36 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, PowScale
         if (kt + 1 < nk) gload((kt + 1) * BK);
         const float *as = As + cur * ABUF;
         const float *bs = Bs + cur * BBUF;
-#pragma unroll
-        for (int q = 0; q < KH / 4; ++q) {
-            f4 a[FM];
+        // Operands of the next group of four k values are read from LDS while
+        // the MFMAs of the current group run (register double buffering).
+        f4 a[2][FM];
+        float b[2][4][FN];
+        auto lds_load = [&](int q, int st) {
 #pragma unroll
             for (int i = 0; i < FM; ++i)
-                a[i] = *(const f4 *)(as + (wm * TM + i * 32 + l32) * ALD + h * KH + 4 * q);
+                a[st][i] = *(const f4 *)(as + (wm * TM + i * 32 + l32) * ALD + h * KH + 4 * q);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                float b[FN];
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    b[j] = bs[(h * KH + 4 * q + t) * BLD + wn * TN + j * 32 + l32];
+                    b[st][t][j] = bs[(h * KH + 4 * q + t) * BLD + wn * TN + j * 32 + l32];
+        };
+        lds_load(0, 0);
+#pragma unroll
+        for (int q = 0; q < KH / 4; ++q) {
+            const int st = q & 1;
+            if (q + 1 < KH / 4) lds_load(q + 1, st ^ 1);
+            // keep the reads above ahead of this group's MFMAs
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t], b[j], acc[i][j],
-                                                                        0, 0, 0);
-            }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][i][t], b[st][t][j],
+                                                                        acc[i][j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();

@@ -64,4 +64,28 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
     return v;
 }
 
+// Tile order for a grid of tilesM x tilesN output tiles.  Workgroups are
+// dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8), and
+// each XCD has its own L2.  The block index is first permuted so that every
+// XCD gets one contiguous range of tiles, and that range is walked in bands
+// of GROUP_M tile rows, column by column, so that the workgroups an XCD runs
+// at the same time share rows of X and columns of Y in its L2.  A bijection
+// of [0, tilesM * tilesN).
+__device__ __forceinline__ void tile_of_block(int b, int tilesM, int tilesN, int *tm, int *tn) {
+    constexpr int XCDS = 8, GROUP_M = 8;
+    const int T = tilesM * tilesN;
+    int t = b;
+    if (T >= 4 * XCDS) {
+        const int x = b % XCDS, local = b / XCDS;
+        const int base = T / XCDS, rem = T % XCDS;
+        t = x * base + (x < rem ? x : rem) + local;
+    }
+    const int band = GROUP_M * tilesN;
+    const int first_m = (t / band) * GROUP_M;
+    const int gm = tilesM - first_m < GROUP_M ? tilesM - first_m : GROUP_M;
+    const int r = t % band;
+    *tm = first_m + r % gm;
+    *tn = r / gm;
+}
+
 }  // namespace mpow

@@ -159,10 +159,10 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     const int grp = lane >> 5, l32 = lane & 31;
-    const int tilesN = (n + BN - 1) / BN;
-    const int tile = blockIdx.x;
-    const int m0 = (tile / tilesN) * BM;
-    const int n0 = (tile % tilesN) * BN;
+    int tm, tn;
+    tile_of_block(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
 
     // 16-byte chunks: a tile row of SBK elements is SBK/8 chunks.
     constexpr int CPR = SBK / 8;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < WM * WN; ++w) t += red[w];
-        g.partC[tile] = t;
+        g.partC[blockIdx.x] = t;
     }
 }
 
