@@ -323,13 +323,82 @@ def serving_workload(args):
     return 0
 
 
+# The paper's timing tables (section 5.2, seconds on a Tesla C2050 and one
+# Xeon core): (N, p) -> (naive GPU, sequential CPU, the paper's method).
+PAPER_TIMES = {
+    (64, 64): (0.05, 0.23, 0.01), (64, 128): (0.14, 0.68, 0.01), (64, 256): (0.43, 1.74, 0.02),
+    (64, 512): (0.99, 4.31, 0.02), (64, 1024): (2.69, 10.83, 0.03),
+    (128, 64): (0.1, 1.83, 0.02), (128, 128): (0.25, 5.72, 0.02), (128, 256): (0.62, 13.18, 0.02),
+    (128, 512): (1.38, 27.53, 0.02),
+    (256, 64): (0.21, 16.0, 0.03), (256, 128): (0.43, 32.19, 0.03), (256, 256): (0.87, 64.61, 0.04),
+    (256, 512): (1.76, 129.38, 0.04),
+    (512, 64): (0.26, 78.49, 0.12), (512, 128): (0.43, 157.62, 0.13), (512, 256): (0.87, 315.74, 0.14),
+}
+
+
+def paper_workload(args):
+    """The paper's table shapes: the logarithmic schedule (mpow_run) against
+    the naive p - 1 chained products on the same GPU (mpow_run_naive) and the
+    sequential naive CPU method (the oracle's three-loop product on one thread,
+    one product timed and multiplied by p - 1)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1204_3052_amd import inputs, mpow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    plan = mpow.mpow_plan_create(0, 512, 0, mpow.MPOW_FP32, 0)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    rows = []
+    cpu_product_s = {}
+    for (n, p), (pg_naive, pg_cpu, pg_ours) in PAPER_TIMES.items():
+        A_np = inputs.gaussian(n, n)
+        A = torch.from_numpy(A_np).to(dev)
+        out = torch.empty_like(A)
+        res = {}
+        for name, fn in (("ours", mpow.mpow_run), ("naive_gpu", mpow.mpow_run_naive)):
+            fn(plan, A.data_ptr(), n, p, out.data_ptr(), sc.data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize(dev)
+            times = []
+            for _ in range(max(args.steps, 1)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn(plan, A.data_ptr(), n, p, out.data_ptr(), sc.data_ptr(), stream.cuda_stream)
+                e1.record(stream)
+                torch.cuda.synchronize(dev)
+                times.append(e0.elapsed_time(e1))
+            res[name] = float(np.median(times)) / 1e3
+        if n not in cpu_product_s:
+            oracle.set_naive_threads(1)
+            X = A_np.astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.matmul_naive(X, X)
+            cpu_product_s[n] = time.perf_counter() - t0
+        cpu_s = cpu_product_s[n] * (p - 1)
+        rows.append({"n": n, "p": p, "ours_s": round(res["ours"], 6), "naive_gpu_s": round(res["naive_gpu"], 6),
+                     "ours_vs_naive_gpu": round(res["naive_gpu"] / res["ours"], 1),
+                     "seq_cpu_s_extrapolated": round(cpu_s, 3),
+                     "ours_vs_seq_cpu": round(cpu_s / res["ours"], 0),
+                     "paper_c2050": {"ours_s": pg_ours, "naive_gpu_s": pg_naive, "seq_cpu_s": pg_cpu,
+                                     "ours_vs_naive_gpu": round(pg_naive / pg_ours, 2)}})
+    mpow.mpow_plan_destroy(plan)
+    print(json.dumps({"workload": "paper table shapes: N in {64,128,256,512}, p in {64..1024}, "
+                                  "N(0,1)/sqrt(N) entries, FP32 products",
+                      "cpu_seq_note": "one FP64 three-loop product on one thread, times (p - 1)",
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched", "serving"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched", "serving", "paper"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
                          "at N=4096, p in {64, 1000}, with errors against the oracle")
     ap.add_argument("--duration", type=float, default=60.0,
@@ -361,6 +430,8 @@ def main():
         return batched_workload(args)
     if args.workload == "serving":
         return serving_workload(args)
+    if args.workload == "paper":
+        return paper_workload(args)
 
     import numpy as np
     import torch
@@ -413,8 +484,8 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = flop_step * args.steps / dt / 1e9
 
-    # dominant kernel: the product kernel used for the large sizes
-    kid = mpow.MPOW_KERNEL_GEMM_F32_128
+    # dominant kernel: the product kernel used for the largest size
+    kid = mpow.MPOW_KERNEL_GEMM_F32_256
     launches, kms, kflop, kname = mpow.mpow_plan_timing(plan, kid)
     achieved = (kflop / launches) / (kms / launches * 1e-3) / 1e12 if launches else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,

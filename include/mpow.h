@@ -74,6 +74,9 @@ typedef enum mpow_mode {
 /* Upper bound on the number of products of one power (p < 2^63 needs <= 124). */
 #define MPOW_MAX_STEPS 126
 
+/* Largest p mpow_run_naive accepts. */
+#define MPOW_NAIVE_MAX_P 4096
+
 typedef struct mpow_plan *mpow_plan_t;
 
 /* Static description of a status code.  Never NULL. */
@@ -125,6 +128,15 @@ mpow_status mpow_plan_destroy(mpow_plan_t plan);
 mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
                      double *log2_scale, void *stream);
 
+/* The paper's naive method (sections 4.1 and 4.2): A^p by p - 1 chained
+ * products X <- X.A (the same float32 product kernels, scaling and output
+ * convention as mpow_run), for comparing against the logarithmic schedule.
+ * Arguments as mpow_run; p must be <= MPOW_NAIVE_MAX_P.  Errors: INVALID
+ * (also p > MPOW_NAIVE_MAX_P), UNSUPPORTED (plan mode other than MPOW_FP32),
+ * DEVICE. */
+mpow_status mpow_run_naive(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
+                           double *log2_scale, void *stream);
+
 /* `count` independent powers in one call: matrix i is A[i] (device pointer,
  * n[i] x n[i]) raised to p[i] into out[i], with log2_scale[i] as in mpow_run
  * (log2_scale itself may be NULL: no scales for any matrix).  A, n, p and out
@@ -167,7 +179,9 @@ enum {
     MPOW_KERNEL_GEMM_F32_32 = 2,  /* float32 product, 32x32 tiles */
     MPOW_KERNEL_GEMM_F16X3_128 = 3,  /* FP16 hi/lo three-product, 128x128 tiles */
     MPOW_KERNEL_GEMM_BF16X3_128 = 4, /* BF16 hi/lo three-product, 128x128 tiles */
-    MPOW_KERNEL_COUNT = 8
+    MPOW_KERNEL_GEMM_F32_256 = 5,    /* float32 product, 256x256 tiles, 8 waves */
+    MPOW_KERNEL_GEMM_F32_128x64 = 6, /* float32 product, 128x64 tiles */
+    MPOW_KERNEL_COUNT = 16
 };
 
 /* Timing of product launches recorded under MPOW_FLAG_TIMING since the last

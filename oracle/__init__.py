@@ -18,6 +18,7 @@ from .mpow_oracle import (  # noqa: F401
     normalize,
     perturbed,
     rel_err,
+    set_naive_threads,
     row_rel_errs,
     schedule,
     to_value,

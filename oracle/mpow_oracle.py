@@ -60,6 +60,8 @@ def _naive_lib():
                                                 ctypes.c_void_p, ctypes.c_int64]
         lib.oracle_naive_matmul_f64.restype = None
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -87,6 +89,11 @@ def matmul(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
 
 def naive_threads() -> int:
     return int(_naive_lib().oracle_num_threads())
+
+
+def set_naive_threads(n: int) -> None:
+    """Thread count of the three-loop product (1: the paper's sequential CPU method)."""
+    _naive_lib().oracle_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -26,6 +26,17 @@ void oracle_naive_matmul_f64(const double *a, const double *b, double *c, int64_
     }
 }
 
+/* Sets the OpenMP thread count for later calls (no effect without OpenMP). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Thread count OpenMP would use for the loop above (1 without OpenMP). */
 int oracle_num_threads(void)
 {

@@ -48,6 +48,7 @@ const char *mpow_status_str(int status) {
         case MPOW_ERR_NOMEM: return "out of memory";
         case MPOW_ERR_DEVICE: return "device error";
         case MPOW_ERR_BUDGET: return "exceeds memory budget";
+        case MPOW_ERR_TIMEOUT: return "timed out";
         default: return "unknown status";
     }
 }
@@ -147,8 +148,10 @@ mpow_status mpow_plan_destroy(mpow_plan_t plan) {
 
 int mpow_last_device_error(mpow_plan_t plan) { return plan ? plan->last_error : 0; }
 
-mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
-                     double *log2_scale, void *stream) {
+namespace {
+
+mpow_status check_run_args(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
+                           double *log2_scale) {
     if (!plan || !A || !out || n < 1 || p < 0) return MPOW_ERR_INVALID;
     if (n > plan->max_n) return MPOW_ERR_INVALID;
     const size_t bytes = (size_t)n * (size_t)n * sizeof(float);
@@ -159,10 +162,33 @@ mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *
     if (log2_scale && (ranges_overlap(log2_scale, sizeof(double), A, bytes) ||
                        ranges_overlap(log2_scale, sizeof(double), out, bytes)))
         return MPOW_ERR_INVALID;
+    return MPOW_SUCCESS;
+}
+
+}  // namespace
+
+mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
+                     double *log2_scale, void *stream) {
+    const mpow_status st = check_run_args(plan, A, n, p, out, log2_scale);
+    if (st != MPOW_SUCCESS) return st;
     DeviceGuard guard(plan->device);
     if (!guard.ok) return device_error(plan, hipErrorInvalidDevice);
     TimingSink *t = (plan->flags & MPOW_FLAG_TIMING) ? &plan->timing : nullptr;
     const hipError_t e = enqueue_power(plan->ws, A, n, p, out, log2_scale, (hipStream_t)stream, t);
+    return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
+}
+
+mpow_status mpow_run_naive(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
+                           double *log2_scale, void *stream) {
+    const mpow_status st = check_run_args(plan, A, n, p, out, log2_scale);
+    if (st != MPOW_SUCCESS) return st;
+    if (p > MPOW_NAIVE_MAX_P) return MPOW_ERR_INVALID;
+    if (plan->mode != MPOW_FP32) return MPOW_ERR_UNSUPPORTED;
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return device_error(plan, hipErrorInvalidDevice);
+    TimingSink *t = (plan->flags & MPOW_FLAG_TIMING) ? &plan->timing : nullptr;
+    const hipError_t e =
+        enqueue_power_naive(plan->ws, A, n, p, out, log2_scale, (hipStream_t)stream, t);
     return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
 }
 

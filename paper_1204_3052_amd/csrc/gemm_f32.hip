@@ -35,16 +35,25 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_f32_kernel(GemmLaunch g) {
 }
 
 struct Variant {
-    int bm, bn, nt;
+    int id, bm, bn, wm, wn;
     const char *name;
 };
 
-// index = MPOW_KERNEL_GEMM_F32_* id
-constexpr Variant kVariants[3] = {
-    {128, 128, 256, "gemm_f32_kernel<128,128,2,2>"},
-    {64, 64, 256, "gemm_f32_kernel<64,64,2,2>"},
-    {32, 32, 64, "gemm_f32_kernel<32,32,1,1>"},
+// Every variant accumulates each output element in the same order (K tiles
+// of 32, same k-to-lane mapping), so they all give bit-identical products.
+constexpr Variant kVariants[] = {
+    {MPOW_KERNEL_GEMM_F32_128, 128, 128, 2, 2, "gemm_f32_kernel<128,128,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_64, 64, 64, 2, 2, "gemm_f32_kernel<64,64,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_32, 32, 32, 1, 1, "gemm_f32_kernel<32,32,1,1>"},
+    {MPOW_KERNEL_GEMM_F32_256, 256, 256, 2, 4, "gemm_f32_kernel<256,256,2,4>"},
+    {MPOW_KERNEL_GEMM_F32_128x64, 128, 64, 2, 2, "gemm_f32_kernel<128,64,2,2>"},
 };
+
+const Variant *variant(int id) {
+    for (const Variant &v : kVariants)
+        if (v.id == id) return &v;
+    return nullptr;
+}
 
 template <int BM, int BN, int WM, int WN>
 hipError_t launch_variant(const GemmLaunch &g, bool vec4, hipStream_t s) {
@@ -60,20 +69,25 @@ hipError_t launch_variant(const GemmLaunch &g, bool vec4, hipStream_t s) {
 
 }  // namespace
 
+// Default product kernel per size: large tiles where there are enough of
+// them to fill 256 CUs, smaller ones (more workgroups) below.
 int gemm_pick(int n) {
-    if (n >= 1024) return MPOW_KERNEL_GEMM_F32_128;
+    if (n >= 4096) return MPOW_KERNEL_GEMM_F32_256;
+    if (n >= 1024) return MPOW_KERNEL_GEMM_F32_128x64;
     if (n >= 256) return MPOW_KERNEL_GEMM_F32_64;
     return MPOW_KERNEL_GEMM_F32_32;
 }
 
+bool gemm_is_f32(int kernel) { return variant(kernel) != nullptr; }
+
 int gemm_tiles(int kernel, int n) {
-    const Variant &v = kVariants[kernel];
-    return ((n + v.bm - 1) / v.bm) * ((n + v.bn - 1) / v.bn);
+    const Variant *v = variant(kernel);
+    return ((n + v->bm - 1) / v->bm) * ((n + v->bn - 1) / v->bn);
 }
 
 const char *gemm_name(int kernel) {
-    if (kernel < 0 || kernel >= 3) return nullptr;
-    return kVariants[kernel].name;
+    const Variant *v = variant(kernel);
+    return v ? v->name : nullptr;
 }
 
 hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s) {
@@ -81,6 +95,13 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
         case MPOW_KERNEL_GEMM_F32_128: return launch_variant<128, 128, 2, 2>(g, vec4, s);
         case MPOW_KERNEL_GEMM_F32_64: return launch_variant<64, 64, 2, 2>(g, vec4, s);
         case MPOW_KERNEL_GEMM_F32_32: return launch_variant<32, 32, 1, 1>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_256:
+            // 16-byte loads only: the 4-byte-load form of this tile would spill
+            if (!vec4) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true>),
+                               dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
+            return hipGetLastError();
+        case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, s);
         default: return hipErrorInvalidValue;
     }
 }

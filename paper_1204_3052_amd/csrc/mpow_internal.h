@@ -64,6 +64,9 @@ struct TimingSink {
 // Arguments must already be validated.  Returns the first HIP error.
 hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                          double *log2_scale, hipStream_t s, TimingSink *timing);
+// The naive method: p - 1 chained float32 products X <- X.A (p <= MPOW_NAIVE_MAX_P).
+hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64_t p, float *out,
+                               double *log2_scale, hipStream_t s, TimingSink *timing);
 
 // ---------------------------------------------------------------- kernels
 
@@ -109,18 +112,20 @@ const char *gemm_split_name(int kernel);
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s);
 
 // Float32 product kernel variants (index = MPOW_KERNEL_* id).
-int gemm_pick(int n);                       // kernel id used for size n
+int gemm_pick(int n);                       // default kernel id for size n
+bool gemm_is_f32(int kernel);
 int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
 const char *gemm_name(int kernel);
 hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s);
 
 // Scale and bookkeeping kernels.
+constexpr int kMaxNormBlocks = 1024;  // partial sums of A (capacity of Workspace::partA)
 int norm_blocks(int n);
 hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s);
 hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s);
 hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
                          const int *escale, int64_t p, float *out, double *log2_scale,
-                         hipStream_t s);
+                         hipStream_t s, int naive_steps = -1);
 
 // ---------------------------------------------------------------- ragged batch
 

@@ -22,8 +22,8 @@ Layout layout_for(int max_n, int mode) {
     const size_t t32 = (n + 31) / 32;  // the smallest product tile is 32 x 32
     z.buf = round_up(n * n * sizeof(float), 256);
     z.part = round_up(t32 * t32 * sizeof(double), 256);
-    z.partA = round_up(512 * sizeof(double), 256);
-    z.escale = round_up((MPOW_MAX_STEPS + 2) * sizeof(int), 256);
+    z.partA = round_up(kMaxNormBlocks * sizeof(double), 256);
+    z.escale = round_up((MPOW_NAIVE_MAX_P + 2) * sizeof(int), 256);
     const size_t ld = (size_t)split_ld(max_n);
     z.split = mode == MPOW_FP32 ? 0 : round_up(ld * ld * 2, 256);
     z.total = 2 * z.buf + 2 * z.part + z.partA + z.escale + 8 * z.split;
@@ -138,9 +138,10 @@ int schedule_of(int64_t p, uint8_t *ops) {
 hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const uint8_t *ops,
                     int G, int nbA, float *out, double *log2_scale, hipStream_t s,
                     TimingSink *timing) {
-    const int kernel = gemm_pick(n);
-    const int tiles = gemm_tiles(kernel, n);
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    int kernel = gemm_pick(n);
+    if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
+    const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
     const float *X = A;
     const double *partX = ws.partA;
@@ -241,6 +242,44 @@ hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, 
     if (G == 0) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     if (ws.mode != MPOW_FP32) return run_split(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
     return run_fp32(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
+}
+
+hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64_t p, float *out,
+                               double *log2_scale, hipStream_t s, TimingSink *timing) {
+    if (p == 0) return launch_identity(out, n, log2_scale, s);
+    const int nbA = norm_blocks(n);
+    MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
+    if (p == 1) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
+    const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    int kernel = gemm_pick(n);
+    if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
+    const int tiles = gemm_tiles(kernel, n);
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+    const int G = (int)(p - 1);
+    const float *X = A;
+    const double *partX = ws.partA;
+    int nPartX = nbA;
+    for (int k = 1; k <= G; ++k) {
+        GemmLaunch g;
+        g.X = X;
+        g.partX = partX;
+        g.nPartX = nPartX;
+        g.Y = A;
+        g.partY = ws.partA;
+        g.nPartY = nbA;
+        g.C = ws.buf[k & 1];
+        g.partC = ws.part[k & 1];
+        g.eSlot = ws.escale + (k - 1);
+        g.n = n;
+        TimingRecord rec{};
+        if (timing) MPOW_TRY(timing->start(kernel, flop, s, &rec));
+        MPOW_TRY(gemm_launch(kernel, g, vec4, s));
+        if (timing) MPOW_TRY(timing->stop(&rec, s));
+        X = g.C;
+        partX = g.partC;
+        nPartX = tiles;
+    }
+    return launch_finish(X, n, partX, nPartX, ws.escale, p, out, log2_scale, s, G);
 }
 
 // ---------------------------------------------------------------- ragged batch

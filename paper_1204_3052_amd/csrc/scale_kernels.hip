@@ -9,18 +9,47 @@ namespace mpow {
 namespace {
 
 constexpr int kNT = 256;
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Partial sums of squares of A (float64), block b covering one contiguous
-// chunk of the n*n elements in a fixed order.
+// chunk of the n*n elements in a fixed order.  VEC: 16-byte loads (the chunk
+// is a multiple of 4 elements and A is 16-byte aligned), four in flight per
+// thread.
+template <bool VEC>
 __global__ __launch_bounds__(kNT) void sumsq_kernel(const float *__restrict__ A, int64_t total,
                                                     int64_t chunk, double *__restrict__ part) {
     __shared__ double red[kNT];
     const int64_t begin = (int64_t)blockIdx.x * chunk;
     const int64_t end = begin + chunk < total ? begin + chunk : total;
     double acc = 0.0;
-    for (int64_t i = begin + threadIdx.x; i < end; i += kNT) {
-        const double v = (double)A[i];
-        acc += v * v;
+    if (VEC && begin < end) {
+        const f4 *V = (const f4 *)A;
+        const int64_t b4 = begin / 4, e4 = end / 4;
+        int64_t i = b4 + threadIdx.x;
+        for (; i + 3 * kNT < e4; i += 4 * kNT) {
+            f4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = V[i + u * kNT];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc += (double)v[u][c] * (double)v[u][c];
+        }
+        for (; i < e4; i += kNT) {
+            const f4 v = V[i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc += (double)v[c] * (double)v[c];
+        }
+        // the last 1-3 elements when total is not a multiple of 4
+        for (int64_t j = e4 * 4 + threadIdx.x; j < end; j += kNT) {
+            const double v = (double)A[j];
+            acc += v * v;
+        }
+    } else if (!VEC) {
+        for (int64_t i = begin + threadIdx.x; i < end; i += kNT) {
+            const double v = (double)A[i];
+            acc += v * v;
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -47,14 +76,15 @@ __global__ __launch_bounds__(kNT) void identity_kernel(float *__restrict__ out, 
 // where s_G follows from the recorded exponents:
 //   square   : s_k = 2 (s_{k-1} + e_{k-1})
 //   multiply : s_k = s_{k-1} + e_{k-1} + e_0
-// (e_k = floor(log2 ||C_k||_F), C_0 = A, s_0 = 0).
+// (e_k = floor(log2 ||C_k||_F), C_0 = A, s_0 = 0).  The steps are those of
+// the binary schedule of p, or naive_steps multiplications when it is >= 0.
 // log2_scale == NULL: out = C_G * 2^(s_G) rounded to float32 via float64.
 // Otherwise        : out = C_G * 2^(-e_G) and *log2_scale = s_G + e_G, or
 //                    0 when C_G is exactly zero.
 __global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
                                                      const double *__restrict__ partC, int nPartC,
                                                      const int *__restrict__ escale, int64_t p,
-                                                     float *out,
+                                                     int naive_steps, float *out,
                                                      double *__restrict__ log2_scale) {
     // C and out may be the same buffer (p = 1 with out == A): every element is
     // read and then written by the same thread.
@@ -65,7 +95,11 @@ __global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
     const double S = block_sum_partials<kNT>(partC, nPartC, red);
     if (threadIdx.x == 0) {
         double s = 0.0;
-        if (p >= 2) {
+        if (naive_steps > 0) {
+            // chained products X <- X.A: s_k = s_{k-1} + e_{k-1} + e_0
+            const int e0 = escale[0];
+            for (int k = 1; k <= naive_steps; ++k) s = s + (double)escale[k - 1] + (double)e0;
+        } else if (naive_steps < 0 && p >= 2) {
             const int e0 = escale[0];
             int k = 1;
             const int top = 63 - __clzll((unsigned long long)p);
@@ -85,18 +119,33 @@ __global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
     }
     __syncthreads();
     const int64_t total = (int64_t)n * n;
+    const int64_t stride = (int64_t)gridDim.x * kNT;
+    const bool vec = (total % 4 == 0) && ((((uintptr_t)C) | ((uintptr_t)out)) & 15) == 0;
     if (log2_scale) {
         const PowScale f = pow2_neg(sh_eG);
-        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total;
-             i += (int64_t)gridDim.x * kNT)
-            out[i] = C[i] * f.a * f.b;
+        if (vec) {
+            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total / 4; i += stride)
+                ((f4 *)out)[i] = ((const f4 *)C)[i] * f.a * f.b;
+        } else {
+            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total; i += stride)
+                out[i] = C[i] * f.a * f.b;
+        }
     } else {
         double sG = sh_sG;
         sG = sG > 4000.0 ? 4000.0 : (sG < -4000.0 ? -4000.0 : sG);
         const int si = (int)sG;
-        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total;
-             i += (int64_t)gridDim.x * kNT)
-            out[i] = (float)ldexp((double)C[i], si);
+        if (vec) {
+            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total / 4; i += stride) {
+                const f4 c = ((const f4 *)C)[i];
+                f4 o;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[k] = (float)ldexp((double)c[k], si);
+                ((f4 *)out)[i] = o;
+            }
+        } else {
+            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total; i += stride)
+                out[i] = (float)ldexp((double)C[i], si);
+        }
     }
 }
 
@@ -113,14 +162,20 @@ int norm_blocks(int n) {
     const int64_t total = (int64_t)n * n;
     int64_t b = (total + 8191) / 8192;
     if (b < 1) b = 1;
-    if (b > 512) b = 512;
+    if (b > kMaxNormBlocks) b = kMaxNormBlocks;
     return (int)b;
 }
 
 hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s) {
     const int64_t total = (int64_t)n * n;
-    const int64_t chunk = (total + blocks - 1) / blocks;
-    hipLaunchKernelGGL(sumsq_kernel, dim3(blocks), dim3(kNT), 0, s, A, total, chunk, part);
+    int64_t chunk = (total + blocks - 1) / blocks;
+    const bool vec = (((uintptr_t)A) & 15) == 0;
+    if (vec) {
+        chunk = (chunk + 3) / 4 * 4;  // every chunk starts on a 16-byte boundary
+        hipLaunchKernelGGL(sumsq_kernel<true>, dim3(blocks), dim3(kNT), 0, s, A, total, chunk, part);
+    } else {
+        hipLaunchKernelGGL(sumsq_kernel<false>, dim3(blocks), dim3(kNT), 0, s, A, total, chunk, part);
+    }
     return hipGetLastError();
 }
 
@@ -132,9 +187,9 @@ hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s)
 
 hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
                          const int *escale, int64_t p, float *out, double *log2_scale,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(finish_kernel, dim3(grid_for((int64_t)n * n, 512)), dim3(kNT), 0, s, C, n,
-                       partC, nPartC, escale, p, out, log2_scale);
+                         hipStream_t s, int naive_steps) {
+    hipLaunchKernelGGL(finish_kernel, dim3(grid_for((int64_t)n * n, 2048)), dim3(kNT), 0, s, C, n,
+                       partC, nPartC, escale, p, naive_steps, out, log2_scale);
     return hipGetLastError();
 }
 

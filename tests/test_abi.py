@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for code in range(6):
+    for code in range(7):
         assert isinstance(mpow.mpow_status_str(code), str)
     assert mpow.mpow_status_str(99) == "unknown status"
 

@@ -260,3 +260,53 @@ def test_invalid_arguments_with_plan(plan):
     assert lib.mpow_run(plan, A.data_ptr(), 64, 2, A.data_ptr() + 4 * 64, None, s) == mpow.MPOW_ERR_INVALID
     assert lib.mpow_run(plan, A.data_ptr() + 2, 32, 2, out.data_ptr(), None, s) == mpow.MPOW_ERR_INVALID
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------ the naive method (p - 1 products)
+
+def run_naive(plan_handle, A_np, p):
+    import torch
+    n = A_np.shape[0]
+    A = torch.from_numpy(np.ascontiguousarray(A_np, dtype=np.float32)).cuda()
+    out = torch.empty_like(A)
+    s = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    print(f"  [gpu] mpow_run_naive n={n} p={p}", flush=True)
+    mpow.mpow_run_naive(plan_handle, A.data_ptr(), n, p, out.data_ptr(), s.data_ptr(),
+                        torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), float(s.item())
+
+
+@pytest.mark.parametrize("n", [17, 64, 256, 300])
+def test_naive_against_oracle(plan, n):
+    A = inputs.gaussian(n, 40 + n)
+    for p in (0, 1, 2, 3, 17, 64, 255):
+        M, s = run_naive(plan, A, p)
+        ref = oracle.mpow_naive(A, p, product=oracle.matmul)
+        err = oracle.rel_err(M, s, *ref)
+        floor = oracle.floor_estimate(A, p, inputs.relative_signs(n, p), ref=oracle.mpow_binary(A, p))
+        assert err <= tol_fp32(floor), (n, p, err)
+
+
+def test_naive_matches_binary_where_schedules_agree(plan):
+    # p = 2 and p = 3 take the same products in both methods: A.A and (A.A).A
+    A = inputs.gaussian(129, 3)
+    for p in (2, 3):
+        Mn, sn = run_naive(plan, A, p)
+        Mb, sb = run_gpu(plan, A, p)
+        assert np.array_equal(Mn, Mb) and sn == sb
+
+
+def test_naive_permutation_exact_and_limits(plan):
+    n = 50
+    sigma = inputs.permutation_perm(n, 9)
+    P = inputs.permutation_matrix(sigma)
+    tau = np.arange(n)
+    for _ in range(100):
+        tau = sigma[tau]
+    M, s = run_naive(plan, P, 100)
+    assert np.array_equal(oracle.to_value(M, s), inputs.permutation_matrix(tau).astype(np.float64))
+    import torch
+    A = torch.zeros((8, 8), device="cuda")
+    with pytest.raises(mpow.MpowError):
+        mpow.mpow_run_naive(plan, A.data_ptr(), 8, mpow.MPOW_NAIVE_MAX_P + 1, A.data_ptr(), None, None)
