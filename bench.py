@@ -38,16 +38,17 @@ def measured_traffic():
     counter summary, or None when the kernel source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_gemm_f32.txt")
-    src = os.path.join(ROOT, "paper_1204_3052_amd", "csrc", "gemm_f32.hip")
+    csrc = os.path.join(ROOT, "paper_1204_3052_amd", "csrc")
     try:
         kv = {}
         for line in open(path):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha:
-            return None
+        for key, name in (("kernel_source_sha256", "gemm_f32.hip"), ("tile_source_sha256", "gemm_f32_tile.h")):
+            sha = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
+            if kv.get(key) != sha:
+                return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
