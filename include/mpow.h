@@ -52,12 +52,13 @@ typedef enum mpow_status {
 /* Arithmetic of the matrix products.  Inputs and outputs are float32 in every
  * mode; scaling, the log2 scale and the final rescale are the same in all.
  *  MPOW_FP32   float32 MFMA products with float32 accumulation.
- *  MPOW_FP16X3 each scaled operand X' is split into FP16 hi = rn(X') and
- *              lo = rn((X' - hi) 2^11); a product is hi.hi + 2^-11 (hi.lo +
- *              lo.hi) from three FP16 MFMA products with float32
- *              accumulation (about float32 accuracy).
- *  MPOW_BF16X3 the same with BF16 halves and no lo shift (about 16 bits of
- *              operand precision; looser tolerance). */
+ *  MPOW_FP16X3 each scaled operand X' (X times an exact power of two that
+ *              puts it in FP16 range) is split into FP16 hi = rn(X') and
+ *              lo = rn(X' - hi); a product is hi.hi + hi.lo + lo.hi from
+ *              three FP16 MFMA products accumulated in float32 (about
+ *              float32 accuracy).
+ *  MPOW_BF16X3 the same with BF16 halves (about 16 bits of operand
+ *              precision; looser tolerance). */
 typedef enum mpow_mode {
     MPOW_FP32 = 0,
     MPOW_FP16X3 = 1,

@@ -2,16 +2,18 @@
 //
 // Every float32 operand X is written as two 16-bit matrices,
 //   X' = X * 2^(k - e)          (e = floor(log2 ||X||_F), k a fixed shift)
-//   hi = rn16(X'),  lo = rn16((X' - hi) * 2^c)
-// so that X' = hi + 2^-c lo to about 22 bits (FP16, c = 11) or 16 bits
-// (BF16, c = 0).  A product then takes three 16-bit MFMA products with
-// float32 accumulation, dropping the lo*lo term:
-//   X'Y' ~= hi_X hi_Y + 2^-c (hi_X lo_Y + lo_X hi_Y).
-// FP16 keeps the cross terms in their own accumulators so that the 2^-c is
-// applied once, exactly, in float32 at the end; the fixed shift k = 14 puts
-// the largest entry of a normalised matrix (||X'||_F < 2^15) inside FP16
-// range while typical entries stay far above its subnormals.  BF16 has
-// float32's exponent range and needs neither shift.
+//   hi = rn16(X'),  lo = rn16(X' - hi)
+// so that X' = hi + lo to about 22 bits (FP16) or 16 bits (BF16).  A product
+// then takes three 16-bit MFMA products accumulated in one float32
+// accumulator, dropping the lo*lo term:
+//   X'Y' ~= hi_X hi_Y + hi_X lo_Y + lo_X hi_Y.
+// For FP16 the fixed shift k = 14 puts the largest entry of a normalised
+// matrix (||X'||_F < 2^15) inside FP16 range and keeps typical entries, and
+// their lo parts, well above FP16's subnormals (an entry of size 2^-12, the
+// typical one of a normalised 4096 x 4096 matrix, becomes 4 and its lo part
+// about 2^-10).  BF16 has float32's exponent range and needs no shift.  One
+// accumulator instead of separate hi*hi and cross-term accumulators halves
+// the accumulator registers, which lets two waves share a SIMD.
 //
 // split_kernel turns a float32 matrix into hi/lo in two layouts: row-major
 // (the left operand: a lane reads 8 consecutive k of its row) and transposed
@@ -30,14 +32,10 @@ struct SplitTraits;
 template <>
 struct SplitTraits<_Float16> {
     static constexpr int kShift = 14;
-    static constexpr int loShift = 11;
-    static constexpr bool twoAcc = true;
 };
 template <>
 struct SplitTraits<__bf16> {
     static constexpr int kShift = 0;
-    static constexpr int loShift = 0;
-    static constexpr bool twoAcc = false;
 };
 
 typedef float v16f __attribute__((ext_vector_type(16)));
@@ -84,7 +82,6 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
     const int eX = exponent_of_sumsq(block_sum_partials<256>(s.part, s.nPart, red));
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && s.eSlot) *s.eSlot = eX;
     const PowScale f = pow2_neg(eX - Tr::kShift);
-    const float cScale = (float)(1 << Tr::loShift);
     const int r0 = blockIdx.y * STS, c0 = blockIdx.x * STS;
     const bool vec = (n % 4) == 0;
 
@@ -108,7 +105,7 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
         for (int t = 0; t < 4; ++t) {
             const float x = v[t] * f.a * f.b;
             h[t] = (T)x;
-            l[t] = (T)((x - (float)h[t]) * cScale);
+            l[t] = (T)(x - (float)h[t]);
             th[r][c + t] = h[t];
             tl[r][c + t] = l[t];
         }
@@ -146,7 +143,6 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 32, FN = TN / 32;
-    constexpr int NACC = Tr::twoAcc ? 2 : 1;
 
     __shared__ __attribute__((aligned(16))) T Ah[2][BM * SLD];
     __shared__ __attribute__((aligned(16))) T Al[2][BM * SLD];
@@ -210,15 +206,13 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
         }
     };
 
-    v16f acc[NACC][FM][FN];
+    v16f acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < NACC; ++a)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[a][i][j][r] = 0.f;
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 128).
     const int nk = (n + SBK - 1) / SBK;
@@ -243,27 +237,25 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
                 bh[j] = *(const V8 *)(&Bh[cur][off]);
                 bl[j] = *(const V8 *)(&Bl[cur][off]);
             }
+            // per accumulator: hi.hi, then hi.lo, then lo.hi (fixed order)
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) acc[0][i][j] = mfma16<T>(ah[i], bh[j], acc[0][i][j]);
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<T>(ah[i], bh[j], acc[i][j]);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[NACC - 1][i][j] = mfma16<T>(ah[i], bl[j], acc[NACC - 1][i][j]);
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<T>(ah[i], bl[j], acc[i][j]);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[NACC - 1][i][j] = mfma16<T>(al[i], bh[j], acc[NACC - 1][i][j]);
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<T>(al[i], bh[j], acc[i][j]);
         }
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
 
-    // C = (hh + 2^-c cross) * 2^-2k, both factors exact powers of two.
-    const float cross = 1.0f / (float)(1 << Tr::loShift);
+    // C = acc * 2^-2k, an exact power of two.
     const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
     double ss = 0.0;
     float *__restrict__ C = g.C;
@@ -275,9 +267,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
             for (int r = 0; r < 16; ++r) {
                 const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
                 const int col = n0 + wn * TN + j * 32 + l32;
-                float v = acc[0][i][j][r];
-                if (Tr::twoAcc) v = v + acc[NACC - 1][i][j][r] * cross;
-                v *= outScale;
+                const float v = acc[i][j][r] * outScale;
                 if (row < n && col < n) {
                     C[(int64_t)row * n + col] = v;
                     ss += (double)v * (double)v;
