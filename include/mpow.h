@@ -202,8 +202,8 @@ mpow_status mpow_plan_timing_reset(mpow_plan_t plan);
  * (the same operation as mpow_run) of mixed n, p and mode:
  *  - float32 requests with n <= 256 (and max_batch > 0) wait in one FIFO and
  *    leave together, up to max_batch at a time, as one persistent batched
- *    launch whenever no batch is running; requests arriving meanwhile join
- *    the next batch.
+ *    launch whenever fewer than two batches are in flight (one running, one
+ *    queued behind it); requests arriving meanwhile join the next batch.
  *  - every other request is admitted in arrival order once its workspace
  *    (mpow_workspace_bytes(n, 0, mode)) fits the unused part of the arena and
  *    one of the streams has fewer than 2 requests in flight; it then runs on
@@ -262,8 +262,9 @@ mpow_status mpow_srv_destroy(mpow_srv_t srv);
 
 /* CPU-only run of the same admission and batching policy against a simulated
  * executor (no device is touched): each stream runs its requests one after
- * another at plain_flops, a batch takes launch_overhead_s plus its flops at
- * batch_flops, a request costs launch_overhead_s plus 2 G(p) n^3 flops.
+ * another at plain_flops; batches (at most two in flight) run one after
+ * another, each taking launch_overhead_s plus its flops at batch_flops; a
+ * request costs launch_overhead_s plus 2 G(p) n^3 flops.
  * reqs must be sorted by t_arrive.  results[i] receives the status (SUCCESS or
  * BUDGET), route, stream and simulated admission/start/end times of request i;
  * *peak_bytes the largest arena use.  Errors: INVALID; BUDGET if the policy

@@ -107,7 +107,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         }
     }
     hipError_t e;
-    e = batch_wait_previous(&plan->batch);
+    e = batch_wait_all(&plan->batch);
     if (e != hipSuccess) {
         plan->last_error = (int)e;
         return MPOW_ERR_DEVICE;
@@ -142,10 +142,10 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         st = MPOW_ERR_DEVICE;
 
     BatchLaunch bl;
-    bl.desc = plan->batch.desc;
+    bl.desc = plan->batch.slot[0].desc;
     bl.scratch = plan->batch.scratch;
     bl.slot_floats = plan->batch.slot_floats;
-    BatchHeader *hdr = (BatchHeader *)plan->batch.host;
+    BatchHeader *hdr = (BatchHeader *)plan->batch.slot[0].host;
     BatchItem *items = (BatchItem *)(hdr + 1);
     const size_t bytes = sizeof(BatchHeader) + (size_t)count * sizeof(BatchItem);
 
@@ -167,7 +167,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                     items[i].cfg = shape;
                 }
                 float ms = 0.f;
-                if (hipMemcpyAsync(plan->batch.desc, plan->batch.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+                if (hipMemcpyAsync(plan->batch.slot[0].desc, plan->batch.slot[0].host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
                     hipEventRecord(e0, s) != hipSuccess ||
                     launch_batched(bl, plan->batch.workers, s) != hipSuccess ||
                     hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

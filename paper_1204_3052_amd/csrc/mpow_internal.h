@@ -155,38 +155,49 @@ int batched_cfg_for(int n);
 int batched_occupancy();  // resident workers per CU
 hipError_t launch_batched(const BatchLaunch &b, int grid, hipStream_t s);
 
-// Everything one stream of ragged batches needs: device descriptors and
-// scratch, a pinned host copy of the descriptors, the tile table and an
-// optional captured graph (copy + launch).  One batch in flight at a time.
-struct BatchContext {
+// One descriptor buffer of a batch context: device descriptors, the pinned
+// host copy the descriptor copy reads, a captured graph (copy + launch) and
+// the event recorded after the batch.
+struct BatchSlot {
     void *desc = nullptr;
     void *host = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_count = -1;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+// Everything one stream of ragged batches needs.  Two descriptor slots are
+// used alternately, so the host fills one while the batch of the other runs;
+// both batches share the per-worker scratch, so a batch always waits (on the
+// device) for the previous one.
+struct BatchContext {
+    BatchSlot slot[2];
+    int next = 0;  // slot of the next batch
+    int last = -1; // slot of the previous batch
     float *scratch = nullptr;
     int64_t slot_floats = 0;
     int workers = 0;
     int max_batch = 0;
     int cfg[kTileBuckets] = {};
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_count = -1;
-    hipEvent_t done = nullptr;
-    bool pending = false;
 };
 size_t batch_desc_bytes(int max_batch);
-// Device bytes (descriptors + scratch) for a context.
+// Device bytes (two descriptor buffers + scratch) for a context.
 size_t batch_device_bytes(int max_batch, int bmax, int workers);
 // Sets up a context over [dev, dev + batch_device_bytes(...)); creates the
-// pinned buffer, capture stream and event.
+// pinned buffers, capture stream and events.
 hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax, int workers);
 void batch_context_release(BatchContext *bc);
-// Waits until the previous batch has consumed the pinned descriptors.
-hipError_t batch_wait_previous(BatchContext *bc);
+// Waits until every enqueued batch of the context has finished.
+hipError_t batch_wait_all(BatchContext *bc);
 // Fills descriptors in longest-work-first order and enqueues the batch on s
-// (through the captured graph when use_graph).  scale may be null, or hold a
-// per-item pointer that may itself be null.
+// (through the slot's captured graph when use_graph); returns the event that
+// completes with the batch in *done (may be null).  scale may be null, or
+// hold a per-item pointer that may itself be null.
 hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, const int *n,
                          const int64_t *p, float *const *out, double *const *scale,
-                         hipStream_t s, bool use_graph);
+                         hipStream_t s, bool use_graph, hipEvent_t *done = nullptr);
 
 // Resident workers of the batched kernel on `device` (CUs x occupancy).
 int batch_workers_for(int device);

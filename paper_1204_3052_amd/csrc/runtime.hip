@@ -289,7 +289,7 @@ size_t batch_desc_bytes(int max_batch) {
 }
 
 size_t batch_device_bytes(int max_batch, int bmax, int workers) {
-    return round_up(batch_desc_bytes(max_batch), 256) +
+    return 2 * round_up(batch_desc_bytes(max_batch), 256) +
            round_up((size_t)workers * 2 * (size_t)bmax * bmax * sizeof(float), 256);
 }
 
@@ -302,37 +302,52 @@ int batch_workers_for(int device) {
 }
 
 hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax, int workers) {
-    bc->desc = dev;
-    bc->scratch = (float *)(dev + round_up(batch_desc_bytes(max_batch), 256));
+    const size_t desc = round_up(batch_desc_bytes(max_batch), 256);
+    bc->slot[0].desc = dev;
+    bc->slot[1].desc = dev + desc;
+    bc->scratch = (float *)(dev + 2 * desc);
     bc->slot_floats = (int64_t)bmax * bmax;
     bc->workers = workers;
     bc->max_batch = max_batch;
     for (int b = 0; b < kTileBuckets; ++b) bc->cfg[b] = batched_cfg_for(b * 16);
-    MPOW_TRY(hipHostMalloc(&bc->host, batch_desc_bytes(max_batch), hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k) {
+        MPOW_TRY(hipHostMalloc(&bc->slot[k].host, batch_desc_bytes(max_batch), hipHostMallocDefault));
+        MPOW_TRY(hipEventCreateWithFlags(&bc->slot[k].done, hipEventDisableTiming));
+    }
     MPOW_TRY(hipStreamCreateWithFlags(&bc->capture_stream, hipStreamNonBlocking));
-    MPOW_TRY(hipEventCreateWithFlags(&bc->done, hipEventDisableTiming));
     return hipSuccess;
 }
 
 void batch_context_release(BatchContext *bc) {
-    if (bc->graph_exec) (void)hipGraphExecDestroy(bc->graph_exec);
-    if (bc->done) (void)hipEventDestroy(bc->done);
+    for (int k = 0; k < 2; ++k) {
+        BatchSlot &sl = bc->slot[k];
+        if (sl.graph_exec) (void)hipGraphExecDestroy(sl.graph_exec);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.host) (void)hipHostFree(sl.host);
+    }
     if (bc->capture_stream) (void)hipStreamDestroy(bc->capture_stream);
-    if (bc->host) (void)hipHostFree(bc->host);
     *bc = BatchContext();
 }
 
-hipError_t batch_wait_previous(BatchContext *bc) {
-    if (!bc->pending) return hipSuccess;
-    MPOW_TRY(hipEventSynchronize(bc->done));
-    bc->pending = false;
+hipError_t batch_wait_all(BatchContext *bc) {
+    for (int k = 0; k < 2; ++k) {
+        BatchSlot &sl = bc->slot[k];
+        if (!sl.pending) continue;
+        MPOW_TRY(hipEventSynchronize(sl.done));
+        sl.pending = false;
+    }
     return hipSuccess;
 }
 
 hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, const int *n,
                          const int64_t *p, float *const *out, double *const *scale,
-                         hipStream_t s, bool use_graph) {
-    MPOW_TRY(batch_wait_previous(bc));
+                         hipStream_t s, bool use_graph, hipEvent_t *done) {
+    BatchSlot &sl = bc->slot[bc->next];
+    // The slot's previous batch must have consumed its descriptors.
+    if (sl.pending) {
+        MPOW_TRY(hipEventSynchronize(sl.done));
+        sl.pending = false;
+    }
     // Longest work first: estimated work (G(p) + 1) n^3, ties by input order.
     std::vector<int> order(count);
     std::vector<double> work(count);
@@ -343,7 +358,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         work[i] = (double)(schedule_of(p[i], ops) + 1) * nn * nn * nn;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-    BatchHeader *hdr = (BatchHeader *)bc->host;
+    BatchHeader *hdr = (BatchHeader *)sl.host;
     hdr->counter = 0;
     hdr->count = count;
     hdr->pad[0] = hdr->pad[1] = 0;
@@ -357,19 +372,23 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         items[k].n = n[i];
         items[k].cfg = bc->cfg[(n[i] + 15) / 16];
     }
+    // Batches share the workers' scratch: order this one after the previous
+    // one even when it was enqueued on another stream.
+    if (bc->last >= 0 && bc->slot[bc->last].pending)
+        MPOW_TRY(hipStreamWaitEvent(s, bc->slot[bc->last].done, 0));
     BatchLaunch bl;
-    bl.desc = bc->desc;
+    bl.desc = sl.desc;
     bl.scratch = bc->scratch;
     bl.slot_floats = bc->slot_floats;
     if (use_graph) {
-        if (!bc->graph_exec || bc->graph_count != count) {
-            if (bc->graph_exec) {
-                (void)hipGraphExecDestroy(bc->graph_exec);
-                bc->graph_exec = nullptr;
+        if (!sl.graph_exec || sl.graph_count != count) {
+            if (sl.graph_exec) {
+                (void)hipGraphExecDestroy(sl.graph_exec);
+                sl.graph_exec = nullptr;
             }
             hipGraph_t graph = nullptr;
             MPOW_TRY(hipStreamBeginCapture(bc->capture_stream, hipStreamCaptureModeRelaxed));
-            const hipError_t e1 = hipMemcpyAsync(bc->desc, bc->host, batch_desc_bytes(count),
+            const hipError_t e1 = hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count),
                                                  hipMemcpyHostToDevice, bc->capture_stream);
             const hipError_t e2 = launch_batched(bl, bc->workers, bc->capture_stream);
             const hipError_t e3 = hipStreamEndCapture(bc->capture_stream, &graph);
@@ -377,21 +396,24 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
                 if (graph) (void)hipGraphDestroy(graph);
                 return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
             }
-            const hipError_t e4 = hipGraphInstantiate(&bc->graph_exec, graph, nullptr, nullptr, 0);
+            const hipError_t e4 = hipGraphInstantiate(&sl.graph_exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e4 != hipSuccess) {
-                bc->graph_exec = nullptr;
+                sl.graph_exec = nullptr;
                 return e4;
             }
-            bc->graph_count = count;
+            sl.graph_count = count;
         }
-        MPOW_TRY(hipGraphLaunch(bc->graph_exec, s));
+        MPOW_TRY(hipGraphLaunch(sl.graph_exec, s));
     } else {
-        MPOW_TRY(hipMemcpyAsync(bc->desc, bc->host, batch_desc_bytes(count), hipMemcpyHostToDevice, s));
+        MPOW_TRY(hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count), hipMemcpyHostToDevice, s));
         MPOW_TRY(launch_batched(bl, bc->workers, s));
     }
-    MPOW_TRY(hipEventRecord(bc->done, s));
-    bc->pending = true;
+    MPOW_TRY(hipEventRecord(sl.done, s));
+    sl.pending = true;
+    if (done) *done = sl.done;
+    bc->last = bc->next;
+    bc->next ^= 1;
     return hipSuccess;
 }
 

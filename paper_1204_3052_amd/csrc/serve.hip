@@ -63,9 +63,11 @@ struct mpow_srv {
         hipEvent_t ev;
     };
     std::vector<Flight> plain;
-    std::vector<Req *> batch_reqs;
-    hipEvent_t batch_ev = nullptr;
-    bool batch_busy = false;
+    struct BatchFlight {
+        std::vector<Req *> reqs;
+        hipEvent_t ev;
+    };
+    std::deque<BatchFlight> batches;  // at most 2, completing in order
     std::vector<hipEvent_t> ev_pool;
     size_t arena_in_use = 0, arena_peak = 0;  // mirrored under mu for stats
     int queued = 0, in_flight = 0;
@@ -120,17 +122,16 @@ struct mpow_srv {
                 out[i] = r->out;
                 sc[i] = r->scale;
             }
-            hipError_t e = batch_enqueue(&batch, count, A.data(), n.data(), p.data(), out.data(),
-                                         sc.data(), batch_stream, false);
-            if (e == hipSuccess) e = hipEventRecord(batch_ev, batch_stream);
+            hipEvent_t ev = nullptr;
+            const hipError_t e = batch_enqueue(&batch, count, A.data(), n.data(), p.data(),
+                                               out.data(), sc.data(), batch_stream, false, &ev);
             if (e != hipSuccess) {
                 last_error = (int)e;
                 (void)hipGetLastError();
                 for (Req *r : l.reqs) complete(r, MPOW_ERR_DEVICE, 1);
                 return;
             }
-            batch_reqs = l.reqs;
-            batch_busy = true;
+            batches.push_back({l.reqs, ev});
             return;
         }
         Req *r = l.reqs[0];
@@ -184,22 +185,21 @@ struct mpow_srv {
                 complete(r, q == hipSuccess ? MPOW_SUCCESS : MPOW_ERR_DEVICE, 0);
                 progress = true;
             }
-            if (batch_busy) {
-                const hipError_t q = hipEventQuery(batch_ev);
-                if (q != hipErrorNotReady) {
-                    batch_busy = false;
-                    batch.pending = false;
-                    if (q != hipSuccess) {
-                        last_error = (int)q;
-                        (void)hipGetLastError();
-                    }
-                    for (Req *r : batch_reqs)
-                        complete(r, q == hipSuccess ? MPOW_SUCCESS : MPOW_ERR_DEVICE, 1);
-                    batch_reqs.clear();
-                    progress = true;
+            while (!batches.empty()) {
+                const hipError_t q = hipEventQuery(batches.front().ev);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) {
+                    last_error = (int)q;
+                    (void)hipGetLastError();
                 }
+                for (Req *r : batches.front().reqs)
+                    complete(r, q == hipSuccess ? MPOW_SUCCESS : MPOW_ERR_DEVICE, 1);
+                batches.pop_front();
+                progress = true;
             }
-            const std::vector<Launch> ls = sched->next(!batch_busy);
+            // a second batch may be queued behind a running one: it is
+            // prepared while the first runs and starts as soon as it ends
+            const std::vector<Launch> ls = sched->next(batches.size() < 2);
             for (const Launch &l : ls) launch(l);
             progress = progress || !ls.empty();
             {
@@ -207,10 +207,11 @@ struct mpow_srv {
                 arena_in_use = sched->arena().in_use();
                 arena_peak = sched->arena().peak();
                 queued = (int)sched->queued();
-                in_flight = (int)plain.size() + (int)batch_reqs.size();
+                in_flight = (int)plain.size();
+                for (const BatchFlight &b : batches) in_flight += (int)b.reqs.size();
                 if (!progress && inbox.empty() && !stop)
                     cv.wait_for(lk, std::chrono::microseconds(
-                                        (plain.empty() && !batch_busy) ? 2000 : 20));
+                                        (plain.empty() && batches.empty()) ? 2000 : 20));
             }
         }
     }
@@ -253,14 +254,12 @@ mpow_status mpow_srv_create(mpow_srv_t *out_srv, int device, int max_n, size_t h
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) st = MPOW_ERR_DEVICE;
         else srv->streams.push_back(s);
     }
-    if (st == MPOW_SUCCESS && (hipStreamCreateWithFlags(&srv->batch_stream, hipStreamNonBlocking) != hipSuccess ||
-                               hipEventCreateWithFlags(&srv->batch_ev, hipEventDisableTiming) != hipSuccess))
+    if (st == MPOW_SUCCESS && hipStreamCreateWithFlags(&srv->batch_stream, hipStreamNonBlocking) != hipSuccess)
         st = MPOW_ERR_DEVICE;
     if (st != MPOW_SUCCESS) {
         (void)hipGetLastError();
         for (auto s : srv->streams) (void)hipStreamDestroy(s);
         if (srv->batch_stream) (void)hipStreamDestroy(srv->batch_stream);
-        if (srv->batch_ev) (void)hipEventDestroy(srv->batch_ev);
         batch_context_release(&srv->batch);
         if (srv->batch_dev) (void)hipFree(srv->batch_dev);
         if (srv->arena) (void)hipFree(srv->arena);
@@ -369,7 +368,6 @@ mpow_status mpow_srv_destroy(mpow_srv_t srv) {
         (void)hipStreamDestroy(srv->batch_stream);
     }
     for (auto e : srv->ev_pool) (void)hipEventDestroy(e);
-    if (srv->batch_ev) (void)hipEventDestroy(srv->batch_ev);
     batch_context_release(&srv->batch);
     if (srv->batch_dev) (void)hipFree(srv->batch_dev);
     if (srv->arena) (void)hipFree(srv->arena);
@@ -400,8 +398,11 @@ mpow_status mpow_srv_simulate(const mpow_sim_config *cfg, const mpow_sim_request
         double end;
     };
     std::vector<Fl> plain;
-    std::vector<Req *> batch;
-    double batch_end = -1.0;
+    struct Bt {
+        std::vector<Req *> reqs;
+        double end;
+    };
+    std::deque<Bt> batches;  // at most 2 in flight, run one after another
     int next = 0;
     double t = 0.0;
     int done = 0;
@@ -425,7 +426,7 @@ mpow_status mpow_srv_simulate(const mpow_sim_config *cfg, const mpow_sim_request
         double te = 1e300;
         if (next < count) te = std::min(te, reqs[next].t_arrive);
         for (const Fl &f : plain) te = std::min(te, f.end);
-        if (!batch.empty()) te = std::min(te, batch_end);
+        if (!batches.empty()) te = std::min(te, batches.front().end);
         if (te == 1e300) return MPOW_ERR_INVALID;  // nothing can progress: policy stuck
         t = std::max(t, te);
         for (size_t i = 0; i < plain.size();) {
@@ -439,12 +440,12 @@ mpow_status mpow_srv_simulate(const mpow_sim_config *cfg, const mpow_sim_request
                 ++i;
             }
         }
-        if (!batch.empty() && batch_end <= t) {
-            for (Req *r : batch) {
-                results[r->id].t_end = batch_end;
+        while (!batches.empty() && batches.front().end <= t) {
+            for (Req *r : batches.front().reqs) {
+                results[r->id].t_end = batches.front().end;
                 ++done;
             }
-            batch.clear();
+            batches.pop_front();
         }
         while (next < count && reqs[next].t_arrive <= t) {
             Req *r = &rs[next];
@@ -455,15 +456,17 @@ mpow_status mpow_srv_simulate(const mpow_sim_config *cfg, const mpow_sim_request
             }
             ++next;
         }
-        for (const Launch &l : sched.next(batch.empty())) {
+        for (const Launch &l : sched.next(batches.size() < 2)) {
             if (l.batched) {
                 double f = 0.0;
+                for (Req *r : l.reqs) f += flops(*r);
+                const double start = batches.empty() ? t : std::max(t, batches.back().end);
+                const double end = start + cfg->launch_overhead_s + f / cfg->batch_flops;
                 for (Req *r : l.reqs) {
-                    f += flops(*r);
-                    results[r->id].t_admit = results[r->id].t_start = t;
+                    results[r->id].t_admit = t;
+                    results[r->id].t_start = start;
                 }
-                batch = l.reqs;
-                batch_end = t + cfg->launch_overhead_s + f / cfg->batch_flops;
+                batches.push_back({l.reqs, end});
             } else {
                 Req *r = l.reqs[0];
                 const double start = std::max(t, stream_free[l.stream]);

@@ -310,3 +310,35 @@ def test_naive_permutation_exact_and_limits(plan):
     A = torch.zeros((8, 8), device="cuda")
     with pytest.raises(mpow.MpowError):
         mpow.mpow_run_naive(plan, A.data_ptr(), 8, mpow.MPOW_NAIVE_MAX_P + 1, A.data_ptr(), None, None)
+
+
+# ------------------------------------------------------------ full-size properties (N = 8192)
+
+@pytest.mark.parametrize("p", [256, 1023])
+def test_n8192_row_stochastic_row_sums(plan, p):
+    # Powers of a row-stochastic matrix are row-stochastic: every row of A^p
+    # sums to 1, at any size.  The float32 input's own row sums are 1 only to
+    # about 1e-7, so the bound is a few float32 ulps times the product count.
+    n = 8192
+    A = inputs.row_stochastic(n, 2)
+    out, _ = run_gpu(plan, A, p, log_scale=False)
+    rs = out.astype(np.float64).sum(axis=1)
+    dev = float(np.max(np.abs(rs - 1.0)))
+    print(f"    n=8192 p={p} max row-sum deviation {dev:.3e}")
+    assert dev <= 1e-4
+
+
+def test_n8192_semigroup_of_gpu_powers(plan):
+    # A^(m+n) = A^m A^n checked on sampled rows: rows of the GPU's A^17 against
+    # (rows of the GPU's A^9) times the GPU's A^8, formed in float64 on the host.
+    n = 8192
+    A = inputs.gaussian(n, 1)
+    M17, s17 = run_gpu(plan, A, 17)
+    M9, s9 = run_gpu(plan, A, 9)
+    M8, s8 = run_gpu(plan, A, 8)
+    rows = [0, 4097, 8191]
+    lhs = M17[rows].astype(np.float64)
+    rhs = M9[rows].astype(np.float64) @ M8.astype(np.float64)
+    for k in range(len(rows)):
+        err = oracle.rel_err(rhs[k], s9 + s8, lhs[k], s17)
+        assert err <= 1e-4, (rows[k], err)
