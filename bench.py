@@ -295,6 +295,7 @@ def serving_workload(args):
 
     flop = np.array([gemm_count(int(p)) * 2.0 * float(n) ** 3 for n, p in zip(ns, ps)])
     span = float(np.nanmax(t_end) - np.nanmin(t_sub))
+    fifo = fifo_plain_baseline(t_arr, ns, ps, modes, pool, out, scale, flop)
 
     def pct(x, q):
         x = x[np.isfinite(x)]
@@ -320,8 +321,65 @@ def serving_workload(args):
         "offered_gflops": round(float(flop.sum()) / args.duration / 1e9, 1),
         "span_s": round(span, 3), "wall_s": round(wall, 3), "backpressure_waits": backpressure,
         "arena_peak_bytes": int(stats["arena_peak"]), "arena_budget_bytes": budget,
+        "plain_fifo_baseline": fifo,
         "sample_errors": errs}), flush=True)
     return 0
+
+
+def fifo_plain_baseline(t_arr, ns, ps, modes, pool, out, scale, flop):
+    """The same trace through the plain kernel alone: one plan per mode, one
+    stream, requests run one after another in arrival order (no batching, no
+    overlap).  Latency is arrival to completion seen by the host, as for the
+    server."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    from paper_1204_3052_amd import mpow
+
+    dev = torch.device("cuda:0")
+    plans = {m: mpow.mpow_plan_create(0, 2048, 0, m, 0) for m in (mpow.MPOW_FP32, mpow.MPOW_BF16X3)}
+    stream = torch.cuda.Stream(dev)
+    count = len(t_arr)
+    lat = np.full(count, np.nan)
+    pending = collections.deque()
+    slots = out.shape[0]
+
+    def drain():
+        while pending and pending[0][1].query():
+            i, _, t_sub = pending.popleft()
+            lat[i] = time.perf_counter() - t_sub
+
+    t0 = time.perf_counter()
+    for i in range(count):
+        target = t0 + float(t_arr[i])
+        while True:
+            drain()
+            dt = target - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 2e-4))
+        n, p, m = int(ns[i]), int(ps[i]), int(modes[i])
+        t_sub = time.perf_counter()
+        mpow.mpow_run(plans[m], pool[n].data_ptr(), n, p, out[i % slots].data_ptr(),
+                      scale[i % slots:i % slots + 1].data_ptr(), stream.cuda_stream)
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        pending.append((i, ev, t_sub))
+    while pending:
+        drain()
+        time.sleep(1e-4)
+    span = time.perf_counter() - t0
+    for h in plans.values():
+        mpow.mpow_plan_destroy(h)
+
+    def pct(x, q):
+        return round(float(np.percentile(x, q)) * 1e3, 3)
+
+    return {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": round(float(lat.mean()) * 1e3, 3)},
+            "n_le_256_p99_ms": pct(lat[ns <= 256], 99),
+            "throughput_gflops": round(float(flop.sum()) / span / 1e9, 1), "span_s": round(span, 3)}
 
 
 # The paper's timing tables (section 5.2, seconds on a Tesla C2050 and one

@@ -170,6 +170,18 @@ mpow_status mpow_plan_tile_table(mpow_plan_t plan, int *table, int len, int set)
  * UNSUPPORTED (mode other than MPOW_FP32), NOMEM, DEVICE. */
 mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_t flags);
 
+/* Forces the product kernel that mpow_run / mpow_run_naive use on this plan
+ * for every n (kernel: an MPOW_KERNEL_* id of the plan's mode), or restores
+ * the per-size default (kernel = -1).  The 256x256 float32 kernel needs
+ * 16-byte loads; where n % 4 != 0 or A is not 16-byte aligned the 128x128
+ * kernel runs instead.  Kernels without a K split give bit-identical
+ * results; a K-split kernel (..._K2/_K4/_K8) adds its partial sums in its
+ * own fixed order, so its results are deterministic but may differ from the
+ * others in the last bits.  Not for use while a run on the plan is enqueued
+ * from another thread.  Errors: INVALID (plan NULL, kernel not of the plan's
+ * mode). */
+mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel);
+
 /* The last hipError_t value a call on this plan saw (0 if none). */
 int mpow_last_device_error(mpow_plan_t plan);
 
@@ -182,6 +194,11 @@ enum {
     MPOW_KERNEL_GEMM_BF16X3_128 = 4, /* BF16 hi/lo three-product, 128x128 tiles */
     MPOW_KERNEL_GEMM_F32_256 = 5,    /* float32 product, 256x256 tiles, 8 waves */
     MPOW_KERNEL_GEMM_F32_128x64 = 6, /* float32 product, 128x64 tiles */
+    MPOW_KERNEL_GEMM_F16X3_256 = 7,  /* FP16 hi/lo three-product, 256x256 tiles, 8 waves */
+    MPOW_KERNEL_GEMM_BF16X3_256 = 8, /* BF16 hi/lo three-product, 256x256 tiles, 8 waves */
+    MPOW_KERNEL_GEMM_F32_32_K4 = 9,  /* float32 product, 32x32 tiles, K split over 4 waves */
+    MPOW_KERNEL_GEMM_F32_32_K8 = 10, /* float32 product, 32x32 tiles, K split over 8 waves */
+    MPOW_KERNEL_GEMM_F32_64_K2 = 11, /* float32 product, 64x64 tiles, 2x2 waves, K split in 2 */
     MPOW_KERNEL_COUNT = 16
 };
 

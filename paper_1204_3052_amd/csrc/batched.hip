@@ -48,11 +48,12 @@ template <int BM, int BN, bool VEC>
 __device__ double wg_product(const float *X, int eX, const float *Y, int eY, float *C, int n,
                              float *As, float *Bs, double *red, double *bcast) {
     const int tn = (n + BN - 1) / BN, tm = (n + BM - 1) / BM;
-    const PowScale fx = pow2_neg(eX), fy = pow2_neg(eY);
+    const OperandScales sc{pow2_neg(eX), pow2_neg(eY)};
+    auto scales = [&]() { return sc; };
     double S = 0.0;
     for (int t = 0; t < tm * tn; ++t) {
         const double ts =
-            f32_tile<BM, BN, 2, 2, VEC>(X, fx, Y, fy, C, n, (t / tn) * BM, (t % tn) * BN, As, Bs, red);
+            f32_tile<BM, BN, 2, 2, VEC>(X, Y, scales, C, n, (t / tn) * BM, (t % tn) * BN, As, Bs, red);
         S += ts;  // meaningful in thread 0
     }
     if (threadIdx.x == 0) *bcast = S;

@@ -222,6 +222,19 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
     return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
 }
 
+mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel) {
+    if (!plan) return MPOW_ERR_INVALID;
+    bool ok = kernel == -1;
+    if (!ok && plan->mode == MPOW_FP32) ok = gemm_is_f32(kernel);
+    if (!ok && plan->mode == MPOW_FP16X3)
+        ok = kernel == MPOW_KERNEL_GEMM_F16X3_128 || kernel == MPOW_KERNEL_GEMM_F16X3_256;
+    if (!ok && plan->mode == MPOW_BF16X3)
+        ok = kernel == MPOW_KERNEL_GEMM_BF16X3_128 || kernel == MPOW_KERNEL_GEMM_BF16X3_256;
+    if (!ok) return MPOW_ERR_INVALID;
+    plan->ws.kernel = kernel;
+    return MPOW_SUCCESS;
+}
+
 mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, double *total_ms,
                              double *total_flop, const char **name) {
     if (!plan || !(plan->flags & MPOW_FLAG_TIMING) || kernel < 0 || kernel >= MPOW_KERNEL_COUNT)

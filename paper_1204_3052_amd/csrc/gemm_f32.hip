@@ -10,11 +10,11 @@ namespace mpow {
 
 namespace {
 
-template <int BM, int BN, int WM, int WN, bool VEC>
-__global__ __launch_bounds__(WM *WN * 64) void gemm_f32_kernel(GemmLaunch g) {
-    constexpr int NT = WM * WN * 64;
-    __shared__ __attribute__((aligned(16))) float As[F32TileLds<BM, BN>::A_FLOATS];
-    __shared__ __attribute__((aligned(16))) float Bs[F32TileLds<BM, BN>::B_FLOATS];
+template <int BM, int BN, int WM, int WN, bool VEC, int KS>
+__global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g) {
+    constexpr int NT = WM * WN * KS * 64;
+    __shared__ __attribute__((aligned(16))) float As[F32TileLds<BM, BN, KS>::A_FLOATS];
+    __shared__ __attribute__((aligned(16))) float Bs[F32TileLds<BM, BN, KS>::B_FLOATS];
     __shared__ double red[NT];
 
     const int n = g.n;
@@ -23,30 +23,38 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_f32_kernel(GemmLaunch g) {
     const int m0 = tm * BM;
     const int n0 = tn * BN;
 
-    // Scales of both operands from their partial sums of squares.
-    const int eX = exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red));
-    int eY = eX;
-    if (g.partY != g.partX) eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
-    if (blockIdx.x == 0 && threadIdx.x == 0 && g.eSlot) *g.eSlot = eX;
-
-    const double ss = f32_tile<BM, BN, WM, WN, VEC>(g.X, pow2_neg(eX), g.Y, pow2_neg(eY), g.C, n,
-                                                    m0, n0, As, Bs, red);
+    // Scales of both operands from their partial sums of squares, reduced
+    // while the first tile's loads are in flight.
+    auto scales = [&]() {
+        const int eX = exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red));
+        int eY = eX;
+        if (g.partY != g.partX)
+            eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
+        if (blockIdx.x == 0 && threadIdx.x == 0 && g.eSlot) *g.eSlot = eX;
+        return OperandScales{pow2_neg(eX), pow2_neg(eY)};
+    };
+    const double ss =
+        f32_tile<BM, BN, WM, WN, VEC, KS>(g.X, g.Y, scales, g.C, n, m0, n0, As, Bs, red);
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
 struct Variant {
-    int id, bm, bn, wm, wn;
+    int id, bm, bn, wm, wn, ks;
     const char *name;
 };
 
-// Every variant accumulates each output element in the same order (K tiles
-// of 32, same k-to-lane mapping), so they all give bit-identical products.
+// The variants without a K split accumulate each output element in the same
+// order (K tiles of 32, same k-to-lane mapping), so they give bit-identical
+// products; a K-split variant adds its partial sums in its own fixed order.
 constexpr Variant kVariants[] = {
-    {MPOW_KERNEL_GEMM_F32_128, 128, 128, 2, 2, "gemm_f32_kernel<128,128,2,2>"},
-    {MPOW_KERNEL_GEMM_F32_64, 64, 64, 2, 2, "gemm_f32_kernel<64,64,2,2>"},
-    {MPOW_KERNEL_GEMM_F32_32, 32, 32, 1, 1, "gemm_f32_kernel<32,32,1,1>"},
-    {MPOW_KERNEL_GEMM_F32_256, 256, 256, 2, 4, "gemm_f32_kernel<256,256,2,4>"},
-    {MPOW_KERNEL_GEMM_F32_128x64, 128, 64, 2, 2, "gemm_f32_kernel<128,64,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_128, 128, 128, 2, 2, 1, "gemm_f32_kernel<128,128,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_64, 64, 64, 2, 2, 1, "gemm_f32_kernel<64,64,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_32, 32, 32, 1, 1, 1, "gemm_f32_kernel<32,32,1,1>"},
+    {MPOW_KERNEL_GEMM_F32_256, 256, 256, 2, 4, 1, "gemm_f32_kernel<256,256,2,4>"},
+    {MPOW_KERNEL_GEMM_F32_128x64, 128, 64, 2, 2, 1, "gemm_f32_kernel<128,64,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_32_K4, 32, 32, 1, 1, 4, "gemm_f32_kernel<32,32,1,1,K4>"},
+    {MPOW_KERNEL_GEMM_F32_32_K8, 32, 32, 1, 1, 8, "gemm_f32_kernel<32,32,1,1,K8>"},
+    {MPOW_KERNEL_GEMM_F32_64_K2, 64, 64, 2, 2, 2, "gemm_f32_kernel<64,64,2,2,K2>"},
 };
 
 const Variant *variant(int id) {
@@ -55,27 +63,29 @@ const Variant *variant(int id) {
     return nullptr;
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int KS = 1>
 hipError_t launch_variant(const GemmLaunch &g, bool vec4, hipStream_t s) {
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
+    const dim3 block(WM * WN * KS * 64);
     if (vec4)
-        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true>), dim3(tiles), dim3(WM * WN * 64),
-                           0, s, g);
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true, KS>), dim3(tiles), block, 0, s, g);
     else
-        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false>), dim3(tiles),
-                           dim3(WM * WN * 64), 0, s, g);
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false, KS>), dim3(tiles), block, 0, s, g);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Default product kernel per size: large tiles where there are enough of
-// them to fill 256 CUs, smaller ones (more workgroups) below.
+// Default product kernel per size (measured on MI355X, time per product):
+// below 640 the output tiles alone cannot fill 256 CUs, so 32x32 tiles with
+// the K range split over 4 waves (n = 512: 10.6 us against 19.3 us for 64x64
+// tiles); up to 2048, 64x64 tiles with a 2-way K split (n = 1024: 29 us
+// against 35 us); above, tiles large enough for MFMA-bound throughput.
 int gemm_pick(int n) {
     if (n >= 4096) return MPOW_KERNEL_GEMM_F32_256;
-    if (n >= 1024) return MPOW_KERNEL_GEMM_F32_128x64;
-    if (n >= 256) return MPOW_KERNEL_GEMM_F32_64;
-    return MPOW_KERNEL_GEMM_F32_32;
+    if (n >= 2048) return MPOW_KERNEL_GEMM_F32_128x64;
+    if (n >= 640) return MPOW_KERNEL_GEMM_F32_64_K2;
+    return MPOW_KERNEL_GEMM_F32_32_K4;
 }
 
 bool gemm_is_f32(int kernel) { return variant(kernel) != nullptr; }
@@ -98,10 +108,13 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
         case MPOW_KERNEL_GEMM_F32_256:
             // 16-byte loads only: the 4-byte-load form of this tile would spill
             if (!vec4) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true>),
+            hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1>),
                                dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
             return hipGetLastError();
         case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_32_K4: return launch_variant<32, 32, 1, 1, 4>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_32_K8: return launch_variant<32, 32, 1, 1, 8>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_64_K2: return launch_variant<64, 64, 2, 2, 2>(g, vec4, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -16,9 +16,17 @@
 //  - The epilogue stores C and returns the tile's float64 sum of squares
 //    (fixed reduction order).
 //
-// Every output element is accumulated in the same order whatever BM, BN,
-// WM, WN are (K tiles of 32 in ascending order, the same k-to-lane mapping),
-// so all tile shapes give bit-identical products.
+//  - K split (KS > 1, for small n where output tiles alone cannot fill the
+//    chip): KS groups of WM x WN waves share the output tile; the LDS tile is
+//    32*KS wide in K and group g takes its g-th 32-wide slice, so each group
+//    sums every KS-th slice of K.  The epilogue adds the KS partial tiles in
+//    group order 0, 1, ..., KS-1.
+//
+// With KS = 1 every output element is accumulated in the same order whatever
+// BM, BN, WM, WN are (K tiles of 32 in ascending order, the same k-to-lane
+// mapping), so those tile shapes give bit-identical products.  A K-split
+// shape adds in another (fixed) order: deterministic, not bit-identical to
+// the KS = 1 shapes.
 #pragma once
 
 #include "scale_device.h"
@@ -32,34 +40,47 @@ constexpr int F32_BK = 32;          // K extent of one LDS tile
 constexpr int F32_KH = F32_BK / 2;  // K values fed by each lane half
 constexpr int F32_ALD = F32_BK + 4; // LDS row stride of the X tile (floats)
 
-template <int BM, int BN>
+template <int BM, int BN, int KS = 1>
 struct F32TileLds {
-    static constexpr int BLD = BN + 4;
-    static constexpr int A_FLOATS = 2 * BM * F32_ALD;
-    static constexpr int B_FLOATS = 2 * F32_BK * BLD;
+    static constexpr int BKC = F32_BK * KS;  // K extent of one LDS tile
+    static constexpr int ALD = BKC + 4;      // LDS row stride of the X tile
+    static constexpr int BLD = BN + 4;       // LDS row stride of the Y tile
+    static constexpr int A_FLOATS = 2 * BM * ALD;
+    static constexpr int B_FLOATS = 2 * BKC * BLD;
 };
 
-// All threads of the workgroup (WM*WN waves) must call it.  `As` / `Bs` hold
-// F32TileLds<BM,BN>::A_FLOATS / B_FLOATS floats of LDS, `red` WM*WN doubles.
-// Returns the tile's sum of squares in thread 0 (0 elsewhere).
-template <int BM, int BN, int WM, int WN, bool VEC>
-__device__ __forceinline__ double f32_tile(const float *__restrict__ X, PowScale fx,
-                                           const float *__restrict__ Y, PowScale fy,
-                                           float *__restrict__ C, int n, int m0, int n0,
-                                           float *As, float *Bs, double *red) {
-    constexpr int NT = WM * WN * 64;
+// Operand scales 2^-eX and 2^-eY, returned by the caller's scale function.
+struct OperandScales {
+    PowScale x, y;
+};
+
+// All threads of the workgroup (WM*WN*KS waves) must call it.  `As` / `Bs`
+// hold F32TileLds<BM,BN,KS>::A_FLOATS / B_FLOATS floats of LDS, `red`
+// WM*WN doubles.
+// `scales()` is called by every thread once, after the first tile's global
+// loads are issued (so work it does, such as reducing partial sums, overlaps
+// their latency); it may contain barriers.  Returns the tile's sum of squares
+// in thread 0 (0 elsewhere).
+template <int BM, int BN, int WM, int WN, bool VEC, int KS = 1, typename ScaleFn>
+__device__ __forceinline__ double f32_tile(const float *__restrict__ X, const float *__restrict__ Y,
+                                           ScaleFn scales, float *__restrict__ C, int n, int m0,
+                                           int n0, float *As, float *Bs, double *red) {
+    typedef F32TileLds<BM, BN, KS> L;
+    constexpr int NT = WM * WN * KS * 64;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 32, FN = TN / 32;
-    constexpr int BK = F32_BK, KH = F32_KH, ALD = F32_ALD;
-    constexpr int BLD = F32TileLds<BM, BN>::BLD;
+    constexpr int BK = L::BKC, KH = F32_KH, ALD = L::ALD, BLD = L::BLD;
     constexpr int ABUF = BM * ALD, BBUF = BK * BLD;
     static_assert(FM >= 1 && FN >= 1 && TM % 32 == 0 && TN % 32 == 0, "wave tile");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = wave / WN, wn = wave % WN;
+    const int ks = wave / (WM * WN);          // K-split group
+    const int wmn = wave % (WM * WN);
+    const int wm = wmn / WN, wn = wmn % WN;
     const int h = lane >> 5, l32 = lane & 31;
+    const int kg = ks * F32_BK;  // this group's K slice within an LDS tile
 
     constexpr int AV = VEC ? 4 : 1;          // floats per load
     constexpr int LA = BM * BK / (AV * NT);  // loads per thread, X tile
@@ -108,6 +129,7 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, PowScale
         }
     };
 
+    PowScale fx, fy;
     auto sstore = [&](int buf) {
         float *as = As + buf * ABUF;
         float *bs = Bs + buf * BBUF;
@@ -148,6 +170,11 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, PowScale
 
     const int nk = (n + BK - 1) / BK;
     gload(0);
+    {
+        const OperandScales sc = scales();
+        fx = sc.x;
+        fy = sc.y;
+    }
     sstore(0);
     __syncthreads();
 
@@ -163,12 +190,12 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, PowScale
         auto lds_load = [&](int q, int st) {
 #pragma unroll
             for (int i = 0; i < FM; ++i)
-                a[st][i] = *(const f4 *)(as + (wm * TM + i * 32 + l32) * ALD + h * KH + 4 * q);
+                a[st][i] = *(const f4 *)(as + (wm * TM + i * 32 + l32) * ALD + kg + h * KH + 4 * q);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    b[st][t][j] = bs[(h * KH + 4 * q + t) * BLD + wn * TN + j * 32 + l32];
+                    b[st][t][j] = bs[(kg + h * KH + 4 * q + t) * BLD + wn * TN + j * 32 + l32];
         };
         lds_load(0, 0);
 #pragma unroll
@@ -191,25 +218,57 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, PowScale
         __syncthreads();
     }
 
+    if constexpr (KS > 1) {
+        // Groups 1..KS-1 park their accumulators in the (now idle) LDS tiles;
+        // group 0 adds them in group order.  Layout: [group-1][i][j][r][lane
+        // of the WM*WN waves], so every access is one float per lane.
+        constexpr int PER = WM * WN * 64 * FM * FN * 16;
+        static_assert((KS - 1) * PER <= 2 * ABUF, "K-split partials fit in the X tiles");
+        auto slot = [&](int g, int i, int j, int r) -> float * {
+            return As + (g - 1) * PER + ((i * FN + j) * 16 + r) * (WM * WN * 64) + wmn * 64 + lane;
+        };
+        if (ks > 0) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) *slot(ks, i, j, r) = acc[i][j][r];
+        }
+        __syncthreads();
+        if (ks == 0) {
+#pragma unroll
+            for (int g = 1; g < KS; ++g)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[i][j][r] += *slot(g, i, j, r);
+        }
+    }
+
     // 32x32 accumulator layout: register r of lane l holds row
     // 8*(r/4) + 4*(l/32) + r%4 and column l%32 of the 32x32 block.
-    double ss = 0.0;
+    if (ks == 0) {
+        double ss = 0.0;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int col = n0 + wn * TN + j * 32 + l32;
-                if (row < n && col < n) {
-                    const float v = acc[i][j][r];
-                    C[(int64_t)row * n + col] = v;
-                    ss += (double)v * (double)v;
+                for (int r = 0; r < 16; ++r) {
+                    const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const int col = n0 + wn * TN + j * 32 + l32;
+                    if (row < n && col < n) {
+                        const float v = acc[i][j][r];
+                        C[(int64_t)row * n + col] = v;
+                        ss += (double)v * (double)v;
+                    }
                 }
-            }
-    ss = wave_sum_lane0(ss);
-    if (lane == 0) red[wave] = ss;
+        ss = wave_sum_lane0(ss);
+        if (lane == 0) red[wmn] = ss;
+    }
     __syncthreads();
     double t = 0.0;
     if (tid == 0) {

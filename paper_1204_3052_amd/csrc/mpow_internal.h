@@ -30,6 +30,7 @@ struct Workspace {
     void *sa[4] = {nullptr, nullptr, nullptr, nullptr};
     int max_n = 0;
     int mode = MPOW_FP32;
+    int kernel = -1;  // product kernel forced for every size, -1: per-size default
 };
 
 size_t round_up(size_t x, size_t a);

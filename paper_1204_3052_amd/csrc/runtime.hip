@@ -139,7 +139,7 @@ hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const
                     int G, int nbA, float *out, double *log2_scale, hipStream_t s,
                     TimingSink *timing) {
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = gemm_pick(n);
+    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n);
     if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
@@ -183,7 +183,7 @@ hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, cons
     const int mode = ws.mode;
     const int ld = split_ld(n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
-    const int kernel = gemm_split_pick(mode, n);
+    const int kernel = ws.kernel >= 0 ? ws.kernel : gemm_split_pick(mode, n);
     const int tiles = gemm_split_tiles(kernel, n);
 
     SplitLaunch sl;
@@ -251,7 +251,7 @@ hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64
     MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
     if (p == 1) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = gemm_pick(n);
+    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n);
     if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;

@@ -18,7 +18,7 @@
 // split_kernel turns a float32 matrix into hi/lo in two layouts: row-major
 // (the left operand: a lane reads 8 consecutive k of its row) and transposed
 // (the right operand: row j holds column j, so a lane again reads 8
-// consecutive k).  Both are zero-padded to ld = n rounded up to 128, so the
+// consecutive k).  Both are zero-padded to ld = n rounded up to 256, so the
 // product kernel's loads need no bounds checks.
 #include "mpow_internal.h"
 #include "scale_device.h"
@@ -133,13 +133,13 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
 
 // ------------------------------------------------------------------ product
 
-constexpr int SBK = 32;        // K extent (16-bit elements) of one LDS tile
-constexpr int SLD = SBK + 8;   // LDS row stride, conflict-free 16-byte reads
-
-template <typename T, int BM, int BN, int WM, int WN>
+// SBK is the K extent (16-bit elements) of one LDS tile; rows are padded by 8
+// elements so that 16-byte LDS reads are conflict-free.
+template <typename T, int BM, int BN, int WM, int WN, int SBK>
 __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch g) {
     typedef SplitTraits<T> Tr;
     typedef typename Vec8<T>::type V8;
+    constexpr int SLD = SBK + 8;
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 32, FN = TN / 32;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 128).
+    // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 256).
     const int nk = (n + SBK - 1) / SBK;
     gload(0);
     sstore(0);
@@ -284,17 +284,19 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     }
 }
 
-template <typename T, int BM, int BN, int WM, int WN>
+template <typename T, int BM, int BN, int WM, int WN, int SBK>
 hipError_t launch_gemm_split(const SplitGemmLaunch &g, hipStream_t s) {
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_split_kernel<T, BM, BN, WM, WN>), dim3(tiles), dim3(WM * WN * 64), 0,
-                       s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<T, BM, BN, WM, WN, SBK>), dim3(tiles), dim3(WM * WN * 64),
+                       0, s, g);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int split_ld(int n) { return (n + 127) / 128 * 128; }
+// Padded leading dimension of the split operands: a multiple of the largest
+// product tile, so tiles read zeros past n and need no bounds checks.
+int split_ld(int n) { return (n + 255) / 256 * 256; }
 
 hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
     const int t = sl.ld / STS;
@@ -305,27 +307,44 @@ hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
     return hipGetLastError();
 }
 
+// 256 x 256 tiles (8 waves, each 128 x 64, K tile 16) from this size up:
+// twice the MFMA work per LDS byte of the 128 x 128 tile.  Both accumulate
+// every output in the same order (per 16-wide K chunk: hi.hi, hi.lo, lo.hi),
+// so the two give bit-identical results.
+constexpr int kSplit256From = 2048;
+
 int gemm_split_pick(int mode, int n) {
-    (void)n;
-    return mode == MPOW_FP16X3 ? MPOW_KERNEL_GEMM_F16X3_128 : MPOW_KERNEL_GEMM_BF16X3_128;
+    const bool big = n >= kSplit256From;
+    if (mode == MPOW_FP16X3) return big ? MPOW_KERNEL_GEMM_F16X3_256 : MPOW_KERNEL_GEMM_F16X3_128;
+    return big ? MPOW_KERNEL_GEMM_BF16X3_256 : MPOW_KERNEL_GEMM_BF16X3_128;
+}
+
+static int split_tile_edge(int kernel) {
+    return (kernel == MPOW_KERNEL_GEMM_F16X3_256 || kernel == MPOW_KERNEL_GEMM_BF16X3_256) ? 256 : 128;
 }
 
 int gemm_split_tiles(int kernel, int n) {
-    (void)kernel;
-    const int t = (n + 127) / 128;
+    const int e = split_tile_edge(kernel);
+    const int t = (n + e - 1) / e;
     return t * t;
 }
 
 const char *gemm_split_name(int kernel) {
-    if (kernel == MPOW_KERNEL_GEMM_F16X3_128) return "gemm_split_kernel<_Float16,128,128,2,2>";
-    if (kernel == MPOW_KERNEL_GEMM_BF16X3_128) return "gemm_split_kernel<__bf16,128,128,2,2>";
-    return nullptr;
+    switch (kernel) {
+        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_kernel<_Float16,128,128,2,2,32>";
+        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_kernel<__bf16,128,128,2,2,32>";
+        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_kernel<_Float16,256,256,2,4,16>";
+        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_kernel<__bf16,256,256,2,4,16>";
+        default: return nullptr;
+    }
 }
 
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s) {
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F16X3_128: return launch_gemm_split<_Float16, 128, 128, 2, 2>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X3_128: return launch_gemm_split<__bf16, 128, 128, 2, 2>(g, s);
+        case MPOW_KERNEL_GEMM_F16X3_128: return launch_gemm_split<_Float16, 128, 128, 2, 2, 32>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_128: return launch_gemm_split<__bf16, 128, 128, 2, 2, 32>(g, s);
+        case MPOW_KERNEL_GEMM_F16X3_256: return launch_gemm_split<_Float16, 256, 256, 2, 4, 16>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_256: return launch_gemm_split<__bf16, 256, 256, 2, 4, 16>(g, s);
         default: return hipErrorInvalidValue;
     }
 }

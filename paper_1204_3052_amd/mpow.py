@@ -40,6 +40,11 @@ MPOW_KERNEL_GEMM_F16X3_128 = 3
 MPOW_KERNEL_GEMM_BF16X3_128 = 4
 MPOW_KERNEL_GEMM_F32_256 = 5
 MPOW_KERNEL_GEMM_F32_128x64 = 6
+MPOW_KERNEL_GEMM_F16X3_256 = 7
+MPOW_KERNEL_GEMM_BF16X3_256 = 8
+MPOW_KERNEL_GEMM_F32_32_K4 = 9
+MPOW_KERNEL_GEMM_F32_32_K8 = 10
+MPOW_KERNEL_GEMM_F32_64_K2 = 11
 MPOW_KERNEL_COUNT = 16
 
 # every symbol include/mpow.h declares
@@ -47,7 +52,7 @@ EXPORTS = (
     "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_workspace_bytes",
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
-    "mpow_plan_tile_table", "mpow_plan_autotune",
+    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel",
     "mpow_srv_create", "mpow_srv_submit", "mpow_srv_poll", "mpow_srv_wait_idle", "mpow_srv_stats",
     "mpow_srv_destroy", "mpow_srv_simulate",
 )
@@ -122,6 +127,7 @@ def _load():
         "mpow_plan_timing_reset": (c.c_int, [P]),
         "mpow_plan_tile_table": (c.c_int, [P, P, c.c_int, c.c_int]),
         "mpow_plan_autotune": (c.c_int, [P, c.c_char_p, c.c_uint32]),
+        "mpow_plan_set_kernel": (c.c_int, [P, c.c_int]),
         "mpow_srv_create": (c.c_int, [c.POINTER(P), c.c_int, c.c_int, c.c_size_t, c.c_int, c.c_int, c.c_uint32]),
         "mpow_srv_submit": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_int, P, P, c.POINTER(c.c_uint64)]),
         "mpow_srv_poll": (c.c_int, [P, c.POINTER(Completion), c.c_int]),
@@ -219,6 +225,11 @@ def mpow_plan_timing(plan: int, kernel: int):
 
 def mpow_plan_timing_reset(plan: int) -> None:
     _check(_load().mpow_plan_timing_reset(plan), "mpow_plan_timing_reset")
+
+
+def mpow_plan_set_kernel(plan: int, kernel: int) -> None:
+    """Forces the plain-path product kernel (-1: per-size default)."""
+    _check(_load().mpow_plan_set_kernel(plan, int(kernel)), "mpow_plan_set_kernel")
 
 
 def mpow_plan_tile_table(plan: int, table=None) -> list:

@@ -81,6 +81,7 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.mpow_run_batched(None, 1, None, None, None, None, None, None) == mpow.MPOW_ERR_INVALID
     assert lib.mpow_plan_timing(None, 0, None, None, None, None) == mpow.MPOW_ERR_INVALID
     assert lib.mpow_plan_timing_reset(None) == mpow.MPOW_ERR_INVALID
+    assert lib.mpow_plan_set_kernel(None, -1) == mpow.MPOW_ERR_INVALID
     assert lib.mpow_plan_destroy(None) == mpow.MPOW_SUCCESS
     assert lib.mpow_last_device_error(None) == 0
 

@@ -342,3 +342,17 @@ def test_n8192_semigroup_of_gpu_powers(plan):
     for k in range(len(rows)):
         err = oracle.rel_err(rhs[k], s9 + s8, lhs[k], s17)
         assert err <= 1e-4, (rows[k], err)
+
+
+def test_embedding_in_larger_matrix_bit_identical(plan):
+    # diag(A, 0) has A's norm and powers diag(A^p, 0): n = 2100 (128 x 64
+    # tiles) and 4100 (256 x 256) must give A's run bit for bit.
+    A = inputs.gaussian(2100, 43)
+    for p in (2, 17):
+        M0, s0 = run_gpu(plan, A, p)
+        B = np.zeros((4100, 4100), np.float32)
+        B[:2100, :2100] = A
+        M1, s1 = run_gpu(plan, B, p)
+        assert s1 == s0
+        assert np.array_equal(M1[:2100, :2100], M0)
+        assert not np.any(M1[2100:, :]) and not np.any(M1[:, 2100:])

@@ -130,3 +130,32 @@ def test_split_input_scaling_exact(mplan):
         M0, s0 = run_gpu(h, A, 17)
         M1, s1 = run_gpu(h, Ak, 17)
         assert np.array_equal(M0, M1) and s1 == s0 + 17 * k
+
+
+def embed(A, m):
+    """diag(A, 0) of size m: its powers are diag(A^p, 0) and its Frobenius
+    norm is A's, so every scale matches A's run."""
+    B = np.zeros((m, m), np.float32)
+    B[:A.shape[0], :A.shape[0]] = A
+    return B
+
+
+def test_split_tile_kernels_bit_identical(mplan):
+    # n = 1030 runs on 128 x 128 tiles and n = 2100 on 256 x 256 tiles; both
+    # add each output's products in the same order, and the extra K range of
+    # the embedding contributes exact zeros.
+    mode, h = mplan
+    A = inputs.gaussian(1030, 41)
+    for p in (2, 17):
+        M0, s0 = run_gpu(h, A, p)
+        M1, s1 = run_gpu(h, embed(A, 2100), p)
+        assert s0 == s1
+        assert np.array_equal(M1[:1030, :1030], M0)
+        assert not np.any(M1[1030:, :]) and not np.any(M1[:, 1030:])
+
+
+def test_split_parity_large_ragged(mplan):
+    mode, h = mplan
+    A = inputs.gaussian(2100, 42)
+    for p in (3, 17):
+        check(mode, h, A, p, p)
