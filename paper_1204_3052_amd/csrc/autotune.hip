@@ -14,7 +14,7 @@ using namespace mpow;
 namespace {
 
 constexpr int kBuckets = kTileBuckets;
-constexpr int kShapes = 4;                     // tile shape ids of the batched kernel
+constexpr int kShapes = kBatchShapes;  // tile shape ids of the batched kernel
 
 struct DevGuard {
     int prev = -1;
@@ -113,8 +113,9 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         return MPOW_ERR_DEVICE;
     }
 
-    const int count = plan->max_batch < 2 * plan->batch.workers ? plan->max_batch
-                                                                : 2 * plan->batch.workers;
+    const int wmax = plan->batch.workers[0] > plan->batch.workers[1] ? plan->batch.workers[0]
+                                                                    : plan->batch.workers[1];
+    const int count = plan->max_batch < 2 * wmax ? plan->max_batch : 2 * wmax;
     const size_t mat = (size_t)bmax * bmax;
     float *in = nullptr, *out = nullptr;
     hipStream_t s = nullptr;
@@ -169,7 +170,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                 float ms = 0.f;
                 if (hipMemcpyAsync(plan->batch.slot[0].desc, plan->batch.slot[0].host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
                     hipEventRecord(e0, s) != hipSuccess ||
-                    launch_batched(bl, plan->batch.workers, s) != hipSuccess ||
+                    launch_batched(bl, plan->batch.workers[shape == 0], shape == 0, s) != hipSuccess ||
                     hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                     st = MPOW_ERR_DEVICE;

@@ -6,9 +6,17 @@
 // until the queue is empty.  Every product is the same float32 tile product
 // as the single-matrix path (f32_tile), looped over the output tiles of the
 // matrix, so each output element is accumulated in exactly the same order as
-// in mpow_run; the running matrices live in two per-worker scratch buffers
-// that stay in L2.  Because one workgroup owns a whole matrix, the per-step
-// Frobenius norm is a workgroup reduction and needs no extra launch.
+// in mpow_run's kernels without a K split; the running matrices live in two
+// per-worker scratch buffers.  Because one workgroup owns a whole matrix, the
+// per-step Frobenius norm is a workgroup reduction and needs no extra launch.
+//
+// Two tile shapes, 128x128 and 64x64 (2x2 waves each), and one load path
+// that picks 16- or 4-byte loads at run time: every extra tile variant in
+// the kernel raises its register allocation (the compiler sizes it for the
+// union of all paths), and with eight variants it reached one workgroup per
+// CU.  A second instance holds only the 64x64 tile (about half the registers
+// and LDS, four workgroups per CU); the host launches it when no matrix of
+// the batch uses the 128x128 tile.
 #include "mpow_internal.h"
 #include "gemm_f32_tile.h"
 
@@ -18,16 +26,40 @@ namespace {
 
 constexpr int kNT = 256;
 
-// Largest LDS footprint among the tile shapes this kernel uses.
-constexpr int kLdsA = F32TileLds<128, 128>::A_FLOATS;
-constexpr int kLdsB = F32TileLds<128, 128>::B_FLOATS;
+// Whole-matrix loops of one workgroup keep kUnroll 16-byte loads in flight
+// per thread (a loop with one load per iteration waits out the memory
+// latency n^2 / 256 times).
+constexpr int kUnroll = 8;
 
-__device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, double *red) {
+__device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, bool vec, double *red) {
     const int64_t total = (int64_t)n * n;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < total; i += kNT) {
-        const double v = (double)M[i];
-        acc += v * v;
+    if (vec) {
+        const f4 *M4 = (const f4 *)M;
+        const int64_t t4 = total / 4;  // total is a multiple of 16 when n % 4 == 0
+        for (int64_t b = threadIdx.x; b < t4; b += kNT * kUnroll) {
+            f4 v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b + (int64_t)u * kNT;
+                v[u] = i < t4 ? M4[i] : f4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc += (double)v[u][c] * (double)v[u][c];
+        }
+    } else {
+        for (int64_t b = threadIdx.x; b < total; b += kNT * kUnroll) {
+            float v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b + (int64_t)u * kNT;
+                v[u] = i < total ? M[i] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) acc += (double)v[u] * (double)v[u];
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -41,19 +73,84 @@ __device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, d
     return S;
 }
 
+// out = X * 2^-e (exact power-of-two scaling, split in two float factors).
+__device__ __forceinline__ void wg_scale_copy(const float *__restrict__ X, float *__restrict__ out,
+                                              int n, bool vec, PowScale f) {
+    const int64_t total = (int64_t)n * n;
+    if (vec) {
+        const f4 *X4 = (const f4 *)X;
+        f4 *O4 = (f4 *)out;
+        const int64_t t4 = total / 4;
+        for (int64_t b = threadIdx.x; b < t4; b += kNT * kUnroll) {
+            f4 v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b + (int64_t)u * kNT;
+                if (i < t4) v[u] = X4[i];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b + (int64_t)u * kNT;
+                if (i < t4) O4[i] = v[u] * f.a * f.b;
+            }
+        }
+    } else {
+        for (int64_t b = threadIdx.x; b < total; b += kNT * kUnroll) {
+            float v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b + (int64_t)u * kNT;
+                if (i < total) v[u] = X[i];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t i = b + (int64_t)u * kNT;
+                if (i < total) out[i] = v[u] * f.a * f.b;
+            }
+        }
+    }
+}
+
+// out = ldexp(X, s) in float64, rounded to float32 (overflow to inf,
+// underflow to zero).
+__device__ __forceinline__ void wg_ldexp_copy(const float *__restrict__ X, float *__restrict__ out,
+                                              int n, int s) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t b = threadIdx.x; b < total; b += kNT * kUnroll) {
+        float v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t i = b + (int64_t)u * kNT;
+            if (i < total) v[u] = X[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t i = b + (int64_t)u * kNT;
+            if (i < total) out[i] = (float)ldexp((double)v[u], s);
+        }
+    }
+}
+
 // One product C = (2^-eX X)(2^-eY Y) over all output tiles of an n x n
 // matrix; returns its sum of squares (tile sums added in tile order) to all
 // threads.
-template <int BM, int BN, bool VEC>
-__device__ double wg_product(const float *X, int eX, const float *Y, int eY, float *C, int n,
-                             float *As, float *Bs, double *red, double *bcast) {
+template <int BM, int BN>
+__device__ __forceinline__ double wg_product(const float *X, int eX, const float *Y, int eY,
+                                             float *C, int n, bool vec, float *As, float *Bs,
+                                             double *red, double *bcast) {
     const int tn = (n + BN - 1) / BN, tm = (n + BM - 1) / BM;
     const OperandScales sc{pow2_neg(eX), pow2_neg(eY)};
     auto scales = [&]() { return sc; };
     double S = 0.0;
     for (int t = 0; t < tm * tn; ++t) {
+        int nn = n, m0 = (t / tn) * BM, n0 = (t % tn) * BN;
+        // Opaque to the optimiser: the tile's per-element address and bounds
+        // arithmetic is then computed inside this loop instead of being
+        // hoisted out of the product loop, where it would hold registers for
+        // the whole matrix.
+        asm volatile("" : "+s"(nn), "+s"(m0), "+s"(n0), "+s"(X), "+s"(Y), "+s"(C));
         const double ts =
-            f32_tile<BM, BN, 2, 2, VEC>(X, Y, scales, C, n, (t / tn) * BM, (t % tn) * BN, As, Bs, red);
+            f32_tile<BM, BN, 2, 2, 2>(X, Y, scales, C, nn, m0, n0, As, Bs, red, vec);
         S += ts;  // meaningful in thread 0
     }
     if (threadIdx.x == 0) *bcast = S;
@@ -63,30 +160,13 @@ __device__ double wg_product(const float *X, int eX, const float *Y, int eY, flo
     return S;
 }
 
-// Tile shape ids: 0 = 128x128, 1 = 64x64, 2 = 128x64, 3 = 64x128 (all with
-// 2x2 waves); every shape gives bit-identical products.
-__device__ double product_dispatch(int cfg, bool vec, const float *X, int eX, const float *Y,
-                                   int eY, float *C, int n, float *As, float *Bs, double *red,
-                                   double *bcast) {
-    switch (cfg) {
-        case 0:
-            return vec ? wg_product<128, 128, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
-                       : wg_product<128, 128, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
-        case 2:
-            return vec ? wg_product<128, 64, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
-                       : wg_product<128, 64, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
-        case 3:
-            return vec ? wg_product<64, 128, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
-                       : wg_product<64, 128, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
-        default:
-            return vec ? wg_product<64, 64, true>(X, eX, Y, eY, C, n, As, Bs, red, bcast)
-                       : wg_product<64, 64, false>(X, eX, Y, eY, C, n, As, Bs, red, bcast);
-    }
-}
-
+// Tile shape ids: 0 = 128x128, 1 = 64x64; both give bit-identical products.
+// BIG = false: the instance without the 128x128 tile (every cfg runs 64x64).
+template <bool BIG>
 __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
-    __shared__ __attribute__((aligned(16))) float As[kLdsA];
-    __shared__ __attribute__((aligned(16))) float Bs[kLdsB];
+    constexpr int TB = BIG ? 128 : 64;  // largest tile edge of this instance
+    __shared__ __attribute__((aligned(16))) float As[F32TileLds<TB, TB>::A_FLOATS];
+    __shared__ __attribute__((aligned(16))) float Bs[F32TileLds<TB, TB>::B_FLOATS];
     __shared__ double red[kNT];
     __shared__ double bcast;
     __shared__ int claimed;
@@ -120,7 +200,7 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
         }
 
         const bool vec = (n % 4 == 0) && (((uintptr_t)item.A & 15) == 0);
-        const double SA = wg_sumsq(item.A, n, red);
+        const double SA = wg_sumsq(item.A, n, vec, red);
         const int eA = exponent_of_sumsq(SA);
         const float *X = item.A;  // running matrix; its true value is X * 2^s
         int eX = eA;
@@ -136,7 +216,10 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
                     float *C = (k & 1) ? S1 : S0;
                     const float *Y = mul ? item.A : X;
                     const int eY = mul ? eA : eX;
-                    SX = product_dispatch(item.cfg, vec, X, eX, Y, eY, C, n, As, Bs, red, &bcast);
+                    if (BIG && item.cfg == 0)
+                        SX = wg_product<TB, TB>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+                    else
+                        SX = wg_product<64, 64>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
                     s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
                     X = C;
                     eX = exponent_of_sumsq(SX);
@@ -147,15 +230,13 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
 
         // finish: the same arithmetic as the single-matrix finish step
         if (item.scale) {
-            const PowScale f = pow2_neg(eX);
-            for (int64_t i = threadIdx.x; i < total; i += kNT) item.out[i] = X[i] * f.a * f.b;
+            const bool vec_out = (n % 4 == 0) && ((((uintptr_t)item.out | (uintptr_t)X) & 15) == 0);
+            wg_scale_copy(X, item.out, n, vec_out, pow2_neg(eX));
             if (threadIdx.x == 0) *item.scale = (SX == 0.0) ? 0.0 : s + (double)eX;
         } else {
             double sc = s;
             sc = sc > 4000.0 ? 4000.0 : (sc < -4000.0 ? -4000.0 : sc);
-            const int si = (int)sc;
-            for (int64_t i = threadIdx.x; i < total; i += kNT)
-                item.out[i] = (float)ldexp((double)X[i], si);
+            wg_ldexp_copy(X, item.out, n, (int)sc);
         }
         __syncthreads();
     }
@@ -170,15 +251,20 @@ int batched_cfg_for(int n) {
     return p128 * p128 <= p64 * p64 ? 0 : 1;
 }
 
-int batched_occupancy() {
+int batched_occupancy(bool big) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel, kNT, 0) != hipSuccess)
-        return 1;
+    const hipError_t e =
+        big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<true>, kNT, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<false>, kNT, 0);
+    if (e != hipSuccess) return 1;
     return blocks < 1 ? 1 : blocks;
 }
 
-hipError_t launch_batched(const BatchLaunch &b, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(kNT), 0, s, b);
+hipError_t launch_batched(const BatchLaunch &b, int grid, bool big, hipStream_t s) {
+    if (big)
+        hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(kNT), 0, s, b);
+    else
+        hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(kNT), 0, s, b);
     return hipGetLastError();
 }
 

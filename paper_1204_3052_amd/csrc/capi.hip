@@ -26,7 +26,7 @@ mpow_status device_error(mpow_plan *plan, hipError_t e) {
     return MPOW_ERR_DEVICE;
 }
 
-constexpr int kWorkersForSizing = 512;  // 256 CUs x 2 resident workers
+constexpr int kWorkersForSizing = 1024;  // 256 CUs x 4 resident workers
 
 int batch_bmax(int max_n) { return max_n < kBatchMaxN ? max_n : kBatchMaxN; }
 
@@ -95,13 +95,11 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     }
     DeviceGuard guard(device);
     if (!guard.ok) return MPOW_ERR_DEVICE;
-    int workers = 0;
-    if (max_batch > 0) {
-        workers = batch_workers_for(device);
-        if (workers < 1) return MPOW_ERR_DEVICE;
-    }
+    int workers[2] = {0, 0};
+    if (max_batch > 0 && !batch_workers_for(device, workers)) return MPOW_ERR_DEVICE;
+    const int wmax = workers[0] > workers[1] ? workers[0] : workers[1];
     const size_t ws_bytes = workspace_bytes(max_n, mode);
-    const size_t b_bytes = max_batch > 0 ? batch_device_bytes(max_batch, batch_bmax(max_n), workers) : 0;
+    const size_t b_bytes = max_batch > 0 ? batch_device_bytes(max_batch, batch_bmax(max_n), wmax) : 0;
 
     mpow_plan *plan = new (std::nothrow) mpow_plan();
     if (!plan) return MPOW_ERR_NOMEM;

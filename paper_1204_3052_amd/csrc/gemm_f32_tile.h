@@ -61,10 +61,16 @@ struct OperandScales {
 // loads are issued (so work it does, such as reducing partial sums, overlaps
 // their latency); it may contain barriers.  Returns the tile's sum of squares
 // in thread 0 (0 elsewhere).
-template <int BM, int BN, int WM, int WN, bool VEC, int KS = 1, typename ScaleFn>
+//
+// VEC selects the global loads: 0 = 4-byte loads (any n and alignment),
+// 1 = 16-byte loads (n % 4 == 0, X and Y 16-byte aligned), 2 = chosen at run
+// time by `vec` with the register footprint of 1 (for kernels that handle
+// both cases and must not carry two copies of the tile loop).
+template <int BM, int BN, int WM, int WN, int VEC, int KS = 1, typename ScaleFn>
 __device__ __forceinline__ double f32_tile(const float *__restrict__ X, const float *__restrict__ Y,
                                            ScaleFn scales, float *__restrict__ C, int n, int m0,
-                                           int n0, float *As, float *Bs, double *red) {
+                                           int n0, float *As, float *Bs, double *red,
+                                           bool vec = VEC == 1) {
     typedef F32TileLds<BM, BN, KS> L;
     constexpr int NT = WM * WN * KS * 64;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -82,34 +88,43 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, const fl
     const int h = lane >> 5, l32 = lane & 31;
     const int kg = ks * F32_BK;  // this group's K slice within an LDS tile
 
-    constexpr int AV = VEC ? 4 : 1;          // floats per load
-    constexpr int LA = BM * BK / (AV * NT);  // loads per thread, X tile
-    constexpr int LB = BK * BN / (AV * NT);  // loads per thread, Y tile
+    constexpr bool V4 = VEC != 0;            // vector register layout
+    constexpr int AV = V4 ? 4 : 1;           // floats per load slot
+    constexpr int LA = BM * BK / (AV * NT);  // load slots per thread, X tile
+    constexpr int LB = BK * BN / (AV * NT);  // load slots per thread, Y tile
     static_assert(LA * AV * NT == BM * BK && LB * AV * NT == BK * BN, "load split");
-    f4 ra[VEC ? LA : 1];
-    f4 rb[VEC ? LB : 1];
-    float sa[VEC ? 1 : LA];
-    float sb[VEC ? 1 : LB];
+    f4 ra[V4 ? LA : 1];
+    f4 rb[V4 ? LB : 1];
+    float sa[V4 ? 1 : LA];
+    float sb[V4 ? 1 : LB];
+
+    // Four consecutive elements of row gr starting at column gc, zero past n.
+    auto load4 = [&](const float *__restrict__ M, int gr, int gc) -> f4 {
+        f4 v = {0.f, 0.f, 0.f, 0.f};
+        if (VEC == 1 || vec) {
+            if (gr < n && gc < n) v = *(const f4 *)(M + (int64_t)gr * n + gc);
+        } else if (gr < n) {
+            const float *p = M + (int64_t)gr * n + gc;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (gc + t < n) v[t] = p[t];
+        }
+        return v;
+    };
 
     auto gload = [&](int k0) {
-        if constexpr (VEC) {
+        if constexpr (V4) {
 #pragma unroll
             for (int r = 0; r < LA; ++r) {
                 const int idx = tid + r * NT;
                 const int row = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-                const int gr = m0 + row, gc = k0 + c;
-                f4 v = {0.f, 0.f, 0.f, 0.f};
-                if (gr < n && gc < n) v = *(const f4 *)(X + (int64_t)gr * n + gc);
-                ra[r] = v;
+                ra[r] = load4(X, m0 + row, k0 + c);
             }
 #pragma unroll
             for (int r = 0; r < LB; ++r) {
                 const int idx = tid + r * NT;
                 const int row = idx / (BN / 4), c = (idx % (BN / 4)) * 4;
-                const int gr = k0 + row, gc = n0 + c;
-                f4 v = {0.f, 0.f, 0.f, 0.f};
-                if (gr < n && gc < n) v = *(const f4 *)(Y + (int64_t)gr * n + gc);
-                rb[r] = v;
+                rb[r] = load4(Y, k0 + row, n0 + c);
             }
         } else {
 #pragma unroll
@@ -133,7 +148,7 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, const fl
     auto sstore = [&](int buf) {
         float *as = As + buf * ABUF;
         float *bs = Bs + buf * BBUF;
-        if constexpr (VEC) {
+        if constexpr (V4) {
 #pragma unroll
             for (int r = 0; r < LA; ++r) {
                 const int idx = tid + r * NT;

@@ -143,7 +143,7 @@ struct BatchItem {
     double *scale;  // null: no log2 scale for this matrix
     int64_t p;
     int n;
-    int cfg;        // tile shape id (0: 128x128, 1: 64x64, 2: 128x64, 3: 64x128)
+    int cfg;        // tile shape id (0: 128x128, 1: 64x64)
 };
 struct BatchLaunch {
     void *desc;           // BatchHeader followed by the items
@@ -152,9 +152,12 @@ struct BatchLaunch {
 };
 constexpr int kBatchMaxN = 256;
 constexpr int kTileBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
+constexpr int kBatchShapes = 2;
 int batched_cfg_for(int n);
-int batched_occupancy();  // resident workers per CU
-hipError_t launch_batched(const BatchLaunch &b, int grid, hipStream_t s);
+// Resident workers per CU of the kernel instance with (big) or without the
+// 128x128 tile.
+int batched_occupancy(bool big);
+hipError_t launch_batched(const BatchLaunch &b, int grid, bool big, hipStream_t s);
 
 // One descriptor buffer of a batch context: device descriptors, the pinned
 // host copy the descriptor copy reads, a captured graph (copy + launch) and
@@ -164,6 +167,7 @@ struct BatchSlot {
     void *host = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_count = -1;
+    bool graph_big = false;
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -178,17 +182,18 @@ struct BatchContext {
     int last = -1; // slot of the previous batch
     float *scratch = nullptr;
     int64_t slot_floats = 0;
-    int workers = 0;
+    int workers[2] = {0, 0};  // [big]: grid of the instance without / with 128x128 tiles
     int max_batch = 0;
     int cfg[kTileBuckets] = {};
     hipStream_t capture_stream = nullptr;
 };
 size_t batch_desc_bytes(int max_batch);
-// Device bytes (two descriptor buffers + scratch) for a context.
+// Device bytes (two descriptor buffers + scratch for `workers` workers).
 size_t batch_device_bytes(int max_batch, int bmax, int workers);
-// Sets up a context over [dev, dev + batch_device_bytes(...)); creates the
-// pinned buffers, capture stream and events.
-hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax, int workers);
+// Sets up a context over [dev, dev + batch_device_bytes(..., max of
+// workers)); creates the pinned buffers, capture stream and events.
+hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax,
+                              const int workers[2]);
 void batch_context_release(BatchContext *bc);
 // Waits until every enqueued batch of the context has finished.
 hipError_t batch_wait_all(BatchContext *bc);
@@ -200,8 +205,9 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
                          const int64_t *p, float *const *out, double *const *scale,
                          hipStream_t s, bool use_graph, hipEvent_t *done = nullptr);
 
-// Resident workers of the batched kernel on `device` (CUs x occupancy).
-int batch_workers_for(int device);
+// Resident workers of each batched kernel instance on `device` (CUs x
+// occupancy; [0] without, [1] with the 128x128 tile); false on failure.
+bool batch_workers_for(int device, int workers[2]);
 
 }  // namespace mpow
 

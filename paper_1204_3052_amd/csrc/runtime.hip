@@ -288,26 +288,33 @@ size_t batch_desc_bytes(int max_batch) {
     return sizeof(BatchHeader) + (size_t)max_batch * sizeof(BatchItem);
 }
 
+// Floats per per-worker scratch buffer: bmax^2 rounded up to 64 floats, so
+// every buffer starts 256-byte aligned (16-byte loads need 16).
+static int64_t batch_slot_floats(int bmax) { return (int64_t)round_up((size_t)bmax * bmax, 64); }
+
 size_t batch_device_bytes(int max_batch, int bmax, int workers) {
     return 2 * round_up(batch_desc_bytes(max_batch), 256) +
-           round_up((size_t)workers * 2 * (size_t)bmax * bmax * sizeof(float), 256);
+           round_up((size_t)workers * 2 * (size_t)batch_slot_floats(bmax) * sizeof(float), 256);
 }
 
-int batch_workers_for(int device) {
+bool batch_workers_for(int device, int workers[2]) {
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        return 0;
-    const int w = cus * batched_occupancy();
-    return w < 1 ? 1 : w;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus < 1)
+        return false;
+    for (int big = 0; big < 2; ++big) workers[big] = cus * batched_occupancy(big != 0);
+    return true;
 }
 
-hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax, int workers) {
+hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax,
+                              const int workers[2]) {
     const size_t desc = round_up(batch_desc_bytes(max_batch), 256);
     bc->slot[0].desc = dev;
     bc->slot[1].desc = dev + desc;
     bc->scratch = (float *)(dev + 2 * desc);
-    bc->slot_floats = (int64_t)bmax * bmax;
-    bc->workers = workers;
+    bc->slot_floats = batch_slot_floats(bmax);
+    bc->workers[0] = workers[0];
+    bc->workers[1] = workers[1];
     bc->max_batch = max_batch;
     for (int b = 0; b < kTileBuckets; ++b) bc->cfg[b] = batched_cfg_for(b * 16);
     for (int k = 0; k < 2; ++k) {
@@ -363,6 +370,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
     hdr->count = count;
     hdr->pad[0] = hdr->pad[1] = 0;
     BatchItem *items = (BatchItem *)(hdr + 1);
+    bool big = false;  // some matrix takes 128x128 tiles: the instance that has them
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
         items[k].A = A[i];
@@ -371,7 +379,9 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         items[k].p = p[i];
         items[k].n = n[i];
         items[k].cfg = bc->cfg[(n[i] + 15) / 16];
+        big = big || items[k].cfg == 0;
     }
+    const int grid = bc->workers[big ? 1 : 0];
     // Batches share the workers' scratch: order this one after the previous
     // one even when it was enqueued on another stream.
     if (bc->last >= 0 && bc->slot[bc->last].pending)
@@ -381,7 +391,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
     bl.scratch = bc->scratch;
     bl.slot_floats = bc->slot_floats;
     if (use_graph) {
-        if (!sl.graph_exec || sl.graph_count != count) {
+        if (!sl.graph_exec || sl.graph_count != count || sl.graph_big != big) {
             if (sl.graph_exec) {
                 (void)hipGraphExecDestroy(sl.graph_exec);
                 sl.graph_exec = nullptr;
@@ -390,7 +400,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
             MPOW_TRY(hipStreamBeginCapture(bc->capture_stream, hipStreamCaptureModeRelaxed));
             const hipError_t e1 = hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count),
                                                  hipMemcpyHostToDevice, bc->capture_stream);
-            const hipError_t e2 = launch_batched(bl, bc->workers, bc->capture_stream);
+            const hipError_t e2 = launch_batched(bl, grid, big, bc->capture_stream);
             const hipError_t e3 = hipStreamEndCapture(bc->capture_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -403,11 +413,12 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
                 return e4;
             }
             sl.graph_count = count;
+            sl.graph_big = big;
         }
         MPOW_TRY(hipGraphLaunch(sl.graph_exec, s));
     } else {
         MPOW_TRY(hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count), hipMemcpyHostToDevice, s));
-        MPOW_TRY(launch_batched(bl, bc->workers, s));
+        MPOW_TRY(launch_batched(bl, grid, big, s));
     }
     MPOW_TRY(hipEventRecord(sl.done, s));
     sl.pending = true;

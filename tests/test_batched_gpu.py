@@ -223,16 +223,20 @@ def test_tile_shapes_bit_identical(plans):
     pk = Packed(mats)
     saved = mpow.mpow_plan_tile_table(hb)
     results = []
-    for shape in range(4):
-        mpow.mpow_plan_tile_table(hb, [shape] * mpow.TILE_TABLE_LEN)
+    # all 128x128, all 64x64 (the instance without the large tile), and a
+    # mix of both shapes in one launch
+    tables = [[0] * mpow.TILE_TABLE_LEN, [1] * mpow.TILE_TABLE_LEN,
+              [b % 2 for b in range(mpow.TILE_TABLE_LEN)]]
+    for table in tables:
+        mpow.mpow_plan_tile_table(hb, table)
         pk.out.fill_(float("nan"))
         run_batch(hb, pk, ps)
         results.append([pk.result(i) for i in range(len(ps))])
     mpow.mpow_plan_tile_table(hb, saved)
-    for shape in range(1, 4):
+    for k in range(1, len(tables)):
         for i in range(len(ps)):
-            assert np.array_equal(results[shape][i][0], results[0][i][0]), (shape, i)
-            assert results[shape][i][1] == results[0][i][1]
+            assert np.array_equal(results[k][i][0], results[0][i][0]), (k, i)
+            assert results[k][i][1] == results[0][i][1]
 
 
 def test_autotune_and_cache(plans, tmp_path):
@@ -241,7 +245,7 @@ def test_autotune_and_cache(plans, tmp_path):
     print("  [gpu] mpow_plan_autotune", flush=True)
     mpow.mpow_plan_autotune(hb, cache, mpow.MPOW_TUNE_FORCE)
     table = mpow.mpow_plan_tile_table(hb)
-    assert all(0 <= t < 4 for t in table)
+    assert all(0 <= t < 2 for t in table)
     text = open(cache).read().splitlines()
     assert text[0].startswith("mpow-tune ") and len(text) == 17
     h2 = mpow.mpow_plan_create(0, 256, 16, mpow.MPOW_FP32, 0)
@@ -251,5 +255,6 @@ def test_autotune_and_cache(plans, tmp_path):
         assert mpow.mpow_plan_tile_table(h2)[1:] == table[1:]
     finally:
         mpow.mpow_plan_destroy(h2)
-    with pytest.raises(mpow.MpowError):
-        mpow.mpow_plan_tile_table(hb, [7] * mpow.TILE_TABLE_LEN)
+    for bad in (2, 7, -1):
+        with pytest.raises(mpow.MpowError):
+            mpow.mpow_plan_tile_table(hb, [bad] * mpow.TILE_TABLE_LEN)
