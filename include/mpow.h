@@ -201,6 +201,7 @@ enum {
     MPOW_KERNEL_GEMM_F32_32_K4 = 9,  /* float32 product, 32x32 tiles, K split over 4 waves */
     MPOW_KERNEL_GEMM_F32_32_K8 = 10, /* float32 product, 32x32 tiles, K split over 8 waves */
     MPOW_KERNEL_GEMM_F32_64_K2 = 11, /* float32 product, 64x64 tiles, 2x2 waves, K split in 2 */
+    MPOW_KERNEL_GEMM_F32_128_K2 = 12, /* float32 product, 128x128 tiles, 2x2 waves, K split in 2 */
     MPOW_KERNEL_COUNT = 16
 };
 

@@ -55,6 +55,7 @@ constexpr Variant kVariants[] = {
     {MPOW_KERNEL_GEMM_F32_32_K4, 32, 32, 1, 1, 4, "gemm_f32_kernel<32,32,1,1,K4>"},
     {MPOW_KERNEL_GEMM_F32_32_K8, 32, 32, 1, 1, 8, "gemm_f32_kernel<32,32,1,1,K8>"},
     {MPOW_KERNEL_GEMM_F32_64_K2, 64, 64, 2, 2, 2, "gemm_f32_kernel<64,64,2,2,K2>"},
+    {MPOW_KERNEL_GEMM_F32_128_K2, 128, 128, 2, 2, 2, "gemm_f32_kernel<128,128,2,2,K2>"},
 };
 
 const Variant *variant(int id) {
@@ -76,14 +77,17 @@ hipError_t launch_variant(const GemmLaunch &g, bool vec4, hipStream_t s) {
 
 }  // namespace
 
-// Default product kernel per size (measured on MI355X, time per product):
-// below 640 the output tiles alone cannot fill 256 CUs, so 32x32 tiles with
-// the K range split over 4 waves (n = 512: 10.6 us against 19.3 us for 64x64
-// tiles); up to 2048, 64x64 tiles with a 2-way K split (n = 1024: 29 us
-// against 35 us); above, tiles large enough for MFMA-bound throughput.
+// Default product kernel per size (measured on MI355X, time per product with
+// each kernel forced): below 640 the output tiles alone cannot fill 256 CUs,
+// so 32x32 tiles with the K range split over 4 waves (n = 512: 10.5 us
+// against 19.2 us for 64x64 tiles); 64x64 tiles with a 2-way K split up to
+// 1792 (n = 1024: 29 us against 35 us); 128x128 tiles with a 2-way K split
+// around 2048 (153 us against 172 us); 64x64 tiles up to 4096 (n = 3072:
+// 549 us against 597 us for 128x64); 256x256 tiles from 4096 on.
 int gemm_pick(int n) {
     if (n >= 4096) return MPOW_KERNEL_GEMM_F32_256;
-    if (n >= 2048) return MPOW_KERNEL_GEMM_F32_128x64;
+    if (n >= 2560) return MPOW_KERNEL_GEMM_F32_64;
+    if (n >= 1792) return MPOW_KERNEL_GEMM_F32_128_K2;
     if (n >= 640) return MPOW_KERNEL_GEMM_F32_64_K2;
     return MPOW_KERNEL_GEMM_F32_32_K4;
 }
@@ -115,6 +119,7 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
         case MPOW_KERNEL_GEMM_F32_32_K4: return launch_variant<32, 32, 1, 1, 4>(g, vec4, s);
         case MPOW_KERNEL_GEMM_F32_32_K8: return launch_variant<32, 32, 1, 1, 8>(g, vec4, s);
         case MPOW_KERNEL_GEMM_F32_64_K2: return launch_variant<64, 64, 2, 2, 2>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_128_K2: return launch_variant<128, 128, 2, 2, 2>(g, vec4, s);
         default: return hipErrorInvalidValue;
     }
 }

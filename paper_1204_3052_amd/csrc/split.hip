@@ -74,6 +74,7 @@ constexpr int STS = 64;  // split tile edge
 template <typename T>
 __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
     typedef SplitTraits<T> Tr;
+    typedef T V4 __attribute__((ext_vector_type(4)));
     __shared__ double red[256];
     __shared__ T th[STS][STS + 8];
     __shared__ T tl[STS][STS + 8];
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && s.eSlot) *s.eSlot = eX;
     const PowScale f = pow2_neg(eX - Tr::kShift);
     const int r0 = blockIdx.y * STS, c0 = blockIdx.x * STS;
-    const bool vec = (n % 4) == 0;
+    const bool vec = (n % 4) == 0 && ((uintptr_t)s.X & 15) == 0;
 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -100,34 +101,33 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
                     if (gc + t < n) v[t] = s.X[(int64_t)gr * n + gc + t];
             }
         }
-        T h[4], l[4];
+        V4 hv, lv;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const float x = v[t] * f.a * f.b;
-            h[t] = (T)x;
-            l[t] = (T)(x - (float)h[t]);
-            th[r][c + t] = h[t];
-            tl[r][c + t] = l[t];
+            const T h = (T)x;
+            const T l = (T)(x - (float)h);
+            hv[t] = h;
+            lv[t] = l;
+            th[r][c + t] = h;
+            tl[r][c + t] = l;
         }
-        T *hp = (T *)s.hi + (int64_t)gr * ld + gc;
-        T *lp = (T *)s.lo + (int64_t)gr * ld + gc;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            hp[t] = h[t];
-            lp[t] = l[t];
-        }
+        // four 16-bit values per 8-byte store (ld and gc are multiples of 4)
+        *(V4 *)((T *)s.hi + (int64_t)gr * ld + gc) = hv;
+        *(V4 *)((T *)s.lo + (int64_t)gr * ld + gc) = lv;
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int c = tid / 16 + 16 * q, r = (tid % 16) * 4;
-        T *hp = (T *)s.hiT + (int64_t)(c0 + c) * ld + r0 + r;
-        T *lp = (T *)s.loT + (int64_t)(c0 + c) * ld + r0 + r;
+        V4 hv, lv;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            hp[t] = th[r + t][c];
-            lp[t] = tl[r + t][c];
+            hv[t] = th[r + t][c];
+            lv[t] = tl[r + t][c];
         }
+        *(V4 *)((T *)s.hiT + (int64_t)(c0 + c) * ld + r0 + r) = hv;
+        *(V4 *)((T *)s.loT + (int64_t)(c0 + c) * ld + r0 + r) = lv;
     }
 }
 

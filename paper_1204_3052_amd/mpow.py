@@ -45,6 +45,7 @@ MPOW_KERNEL_GEMM_BF16X3_256 = 8
 MPOW_KERNEL_GEMM_F32_32_K4 = 9
 MPOW_KERNEL_GEMM_F32_32_K8 = 10
 MPOW_KERNEL_GEMM_F32_64_K2 = 11
+MPOW_KERNEL_GEMM_F32_128_K2 = 12
 MPOW_KERNEL_COUNT = 16
 
 # every symbol include/mpow.h declares

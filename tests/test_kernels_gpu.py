@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 SAME_ORDER = [mpow.MPOW_KERNEL_GEMM_F32_128, mpow.MPOW_KERNEL_GEMM_F32_64, mpow.MPOW_KERNEL_GEMM_F32_32,
               mpow.MPOW_KERNEL_GEMM_F32_256, mpow.MPOW_KERNEL_GEMM_F32_128x64]
 K_SPLIT = [mpow.MPOW_KERNEL_GEMM_F32_32_K4, mpow.MPOW_KERNEL_GEMM_F32_32_K8,
-           mpow.MPOW_KERNEL_GEMM_F32_64_K2]
+           mpow.MPOW_KERNEL_GEMM_F32_64_K2, mpow.MPOW_KERNEL_GEMM_F32_128_K2]
 SIZES = [1, 33, 100, 257, 300, 513, 1030]
 
 
@@ -97,7 +97,7 @@ def test_split_mode_tile_sizes_bit_identical(mode, kernels):
 def test_set_kernel_rejects_other_modes():
     h = mpow.mpow_plan_create(0, 64, 0, mpow.MPOW_FP32, 0)
     try:
-        for bad in (-2, mpow.MPOW_KERNEL_GEMM_F16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256, 12, 99):
+        for bad in (-2, mpow.MPOW_KERNEL_GEMM_F16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256, 13, 99):
             with pytest.raises(mpow.MpowError):
                 mpow.mpow_plan_set_kernel(h, bad)
     finally:

@@ -345,14 +345,14 @@ def test_n8192_semigroup_of_gpu_powers(plan):
 
 
 def test_embedding_in_larger_matrix_bit_identical(plan):
-    # diag(A, 0) has A's norm and powers diag(A^p, 0): n = 2100 (128 x 64
+    # diag(A, 0) has A's norm and powers diag(A^p, 0): n = 2600 (64 x 64
     # tiles) and 4100 (256 x 256) must give A's run bit for bit.
-    A = inputs.gaussian(2100, 43)
+    A = inputs.gaussian(2600, 43)
     for p in (2, 17):
         M0, s0 = run_gpu(plan, A, p)
         B = np.zeros((4100, 4100), np.float32)
-        B[:2100, :2100] = A
+        B[:2600, :2600] = A
         M1, s1 = run_gpu(plan, B, p)
         assert s1 == s0
-        assert np.array_equal(M1[:2100, :2100], M0)
-        assert not np.any(M1[2100:, :]) and not np.any(M1[:, 2100:])
+        assert np.array_equal(M1[:2600, :2600], M0)
+        assert not np.any(M1[2600:, :]) and not np.any(M1[:, 2600:])
