@@ -2,63 +2,24 @@
 // identity for p = 0, and the final rescale that turns the last running
 // matrix into the caller's output (the only float64 arithmetic on the path).
 #include "mpow_internal.h"
-#include "scale_device.h"
+#include "steps_device.h"
 
 namespace mpow {
 
 namespace {
 
 constexpr int kNT = 256;
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Partial sums of squares of A (float64), block b covering one contiguous
-// chunk of the n*n elements in a fixed order.  VEC: 16-byte loads (the chunk
-// is a multiple of 4 elements and A is 16-byte aligned), four in flight per
-// thread.
+// chunk of the n*n elements in a fixed order (sumsq_range).
 template <bool VEC>
 __global__ __launch_bounds__(kNT) void sumsq_kernel(const float *__restrict__ A, int64_t total,
                                                     int64_t chunk, double *__restrict__ part) {
     __shared__ double red[kNT];
     const int64_t begin = (int64_t)blockIdx.x * chunk;
     const int64_t end = begin + chunk < total ? begin + chunk : total;
-    double acc = 0.0;
-    if (VEC && begin < end) {
-        const f4 *V = (const f4 *)A;
-        const int64_t b4 = begin / 4, e4 = end / 4;
-        int64_t i = b4 + threadIdx.x;
-        for (; i + 3 * kNT < e4; i += 4 * kNT) {
-            f4 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = V[i + u * kNT];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc += (double)v[u][c] * (double)v[u][c];
-        }
-        for (; i < e4; i += kNT) {
-            const f4 v = V[i];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc += (double)v[c] * (double)v[c];
-        }
-        // the last 1-3 elements when total is not a multiple of 4
-        for (int64_t j = e4 * 4 + threadIdx.x; j < end; j += kNT) {
-            const double v = (double)A[j];
-            acc += v * v;
-        }
-    } else if (!VEC) {
-        for (int64_t i = begin + threadIdx.x; i < end; i += kNT) {
-            const double v = (double)A[i];
-            acc += v * v;
-        }
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-#pragma unroll
-    for (int s = kNT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    const double S = sumsq_range<kNT, VEC>(A, begin, end, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = S;
 }
 
 __global__ __launch_bounds__(kNT) void identity_kernel(float *__restrict__ out, int n,
@@ -118,35 +79,8 @@ __global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
         if (log2_scale && blockIdx.x == 0) *log2_scale = sh_zero ? 0.0 : s + (double)sh_eG;
     }
     __syncthreads();
-    const int64_t total = (int64_t)n * n;
-    const int64_t stride = (int64_t)gridDim.x * kNT;
-    const bool vec = (total % 4 == 0) && ((((uintptr_t)C) | ((uintptr_t)out)) & 15) == 0;
-    if (log2_scale) {
-        const PowScale f = pow2_neg(sh_eG);
-        if (vec) {
-            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total / 4; i += stride)
-                ((f4 *)out)[i] = ((const f4 *)C)[i] * f.a * f.b;
-        } else {
-            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total; i += stride)
-                out[i] = C[i] * f.a * f.b;
-        }
-    } else {
-        double sG = sh_sG;
-        sG = sG > 4000.0 ? 4000.0 : (sG < -4000.0 ? -4000.0 : sG);
-        const int si = (int)sG;
-        if (vec) {
-            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total / 4; i += stride) {
-                const f4 c = ((const f4 *)C)[i];
-                f4 o;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) o[k] = (float)ldexp((double)c[k], si);
-                ((f4 *)out)[i] = o;
-            }
-        } else {
-            for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < total; i += stride)
-                out[i] = (float)ldexp((double)C[i], si);
-        }
-    }
+    finish_range(C, out, n, log2_scale != nullptr, sh_eG, sh_sG,
+                 (int64_t)blockIdx.x * kNT + threadIdx.x, (int64_t)gridDim.x * kNT);
 }
 
 int grid_for(int64_t total, int cap) {
