@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak (2.4 GHz)
+MFMA_16BIT_PEAK_TFLOPS = 2516.6  # MI355X dense FP16/BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 SIZES = (512, 2048, 8192)
@@ -54,43 +55,55 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(seconds_budget: float = 20.0):
-    """The FP64 oracle on host cores over a bounded sample of the same workload."""
-    import numpy as np
+def blas_threads() -> int:
     from threadpoolctl import threadpool_info
+    return int(max((d.get("num_threads", 1) for d in threadpool_info()
+                    if d.get("user_api") == "blas"), default=1))
 
+
+def oracle_leg(cases, results, seconds_budget: float = 20.0):
+    """The oracle beside the GPU: the FP64 oracle (binary exponentiation,
+    NumPy matmul on the host's cores) runs the benchmark's own cases,
+    smallest first, until about `seconds_budget` seconds of oracle time are
+    used.  Its timed runs give cpu_baseline; on the same reference results
+    (untimed) each GPU result of those cases gets its relative Frobenius error
+    and the stated tolerance (oracle/tolerance.py, floor from one perturbed
+    oracle run).  results[(n, p)] = (M, s) of the GPU, or absent."""
     import oracle
+    from oracle.tolerance import tol_fp32
     from paper_1204_3052_amd import inputs
 
-    threads = max((d.get("num_threads", 1) for d in threadpool_info()
-                   if d.get("user_api") == "blas"), default=1)
-    # the benchmark's own cases, smallest first, until the time budget is used
-    sample = [(n, p) for n in SIZES for p in POWERS]
-    flop = 0.0
-    t0 = time.perf_counter()
-    done = []
-    for n, p in sample:
+    flop, spent, done, errs = 0.0, 0.0, [], {}
+    for n, p in cases:
         A = inputs.gaussian(n, 1)
         t = time.perf_counter()
-        oracle.mpow_binary(A, p)
+        ref = oracle.mpow_binary(A, p)
+        spent += time.perf_counter() - t
         flop += gemm_count(p) * 2.0 * n ** 3
         done.append(f"N={n} p={p}")
-        if time.perf_counter() - t0 > seconds_budget:
+        if (n, p) in results:
+            M, s = results[(n, p)]
+            err = oracle.rel_err(M, s, *ref)
+            floor = oracle.floor_estimate(A, p, inputs.relative_signs(n, 1000 + p), ref=ref)
+            errs[(n, p)] = (err, tol_fp32(floor))
+        if spent > seconds_budget:
             break
-    dt = time.perf_counter() - t0
-    return {"value": flop / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": "FP64 oracle binary exponentiation (numpy matmul) on " + ", ".join(done)
-                      + f"; {dt:.1f} s"}
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": "FP64 oracle binary exponentiation (numpy matmul) on " + ", ".join(done)
+                     + f"; {spent:.1f} s of oracle time"}
+    return cpu, errs
 
 
 def split_workload(args):
     """FP32 vs the two split-precision modes on N=4096, p in {64, 1000}.
-    Same effective-flop formula for every mode; each result's relative
-    Frobenius error against the FP64 oracle is reported beside its rate."""
+    Same effective-flop formula for every mode (G(p) 2N^3); the split modes
+    also report their MFMA rate (three 16-bit products per product) against
+    the FP16/BF16 dense peak.  The oracle leg then reports each result's
+    relative Frobenius error against the FP64 oracle beside its stated
+    tolerance, and the oracle's own rate."""
     import numpy as np
     import torch
 
-    import oracle
     from paper_1204_3052_amd import inputs, mpow
 
     dev = torch.device("cuda:0")
@@ -101,9 +114,9 @@ def split_workload(args):
     out = torch.empty_like(A)
     sc = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    rows = []
-    refs = {p: oracle.mpow_binary(A_np, p) for p in (64, 1000)}
-    for name, mode in (("fp32", mpow.MPOW_FP32), ("fp16x3", mpow.MPOW_FP16X3), ("bf16x3", mpow.MPOW_BF16X3)):
+    rows, kept = [], {}
+    modes = (("fp32", mpow.MPOW_FP32), ("fp16x3", mpow.MPOW_FP16X3), ("bf16x3", mpow.MPOW_BF16X3))
+    for name, mode in modes:
         plan = mpow.mpow_plan_create(0, n, 0, mode, 0)
         for p in (64, 1000):
             run = lambda: mpow.mpow_run(plan, A.data_ptr(), n, p, out.data_ptr(), sc.data_ptr(),
@@ -120,17 +133,54 @@ def split_workload(args):
                 torch.cuda.synchronize(dev)
                 times.append(e0.elapsed_time(e1))
             ms = float(np.median(times))
-            err = oracle.rel_err(out.cpu().numpy(), float(sc.item()), *refs[p])
-            rows.append({"mode": name, "n": n, "p": p, "ms": round(ms, 3),
-                         "gflops": round(gemm_count(p) * 2.0 * n ** 3 / ms / 1e6, 1),
-                         "rel_err": float(f"{err:.3e}")})
+            gflops = gemm_count(p) * 2.0 * n ** 3 / ms / 1e6
+            row = {"mode": name, "n": n, "p": p, "ms": round(ms, 3), "ms_p99": round(float(np.percentile(times, 99)), 3),
+                   "gflops": round(gflops, 1),
+                   "pct_fp32_mfma_peak": round(gflops / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2)}
+            if mode != mpow.MPOW_FP32:
+                row["mfma_pct_of_16bit_peak"] = round(3 * gflops / (MFMA_16BIT_PEAK_TFLOPS * 1e3) * 100, 2)
+            rows.append(row)
+            kept[(name, p)] = (mode, out.cpu().numpy(), float(sc.item()))
         mpow.mpow_plan_destroy(plan)
     fp32 = {r["p"]: r["ms"] for r in rows if r["mode"] == "fp32"}
     for r in rows:
         r["speedup_vs_fp32"] = round(fp32[r["p"]] / r["ms"], 3)
-    print(json.dumps({"workload": "split precision, N=4096 N(0,1)/sqrt(N), p in {64,1000}",
-                      "unit": "GFLOP/s (FP32-equivalent, G(p)*2N^3)", "results": rows}), flush=True)
+    result = {"workload": "split precision, N=4096 N(0,1)/sqrt(N), p in {64,1000}",
+              "unit": "GFLOP/s (FP32-equivalent, G(p)*2N^3)", "results": rows}
+    if not args.no_cpu_baseline:
+        cpu, errs = split_oracle_leg(A_np, kept)
+        result["cpu_baseline"] = cpu
+        for r in rows:
+            err, tol = errs[(r["mode"], r["p"])]
+            r["rel_err"] = float(f"{err:.3e}")
+            r["tol"] = float(f"{tol:.3e}")
+            r["within_tol"] = err <= tol
+    print(json.dumps(result), flush=True)
     return 0
+
+
+def split_oracle_leg(A_np, kept):
+    """The oracle beside the split-precision runs: one FP64 oracle power per p
+    (timed: cpu_baseline), one perturbed run per p for the floor, and every
+    mode's error with its stated tolerance."""
+    import oracle
+    from oracle.tolerance import tol_mode
+    from paper_1204_3052_amd import inputs
+
+    n = A_np.shape[0]
+    flop, spent, errs = 0.0, 0.0, {}
+    for p in (64, 1000):
+        t = time.perf_counter()
+        ref = oracle.mpow_binary(A_np, p)
+        spent += time.perf_counter() - t
+        flop += gemm_count(p) * 2.0 * n ** 3
+        floor = oracle.floor_estimate(A_np, p, inputs.relative_signs(n, 2000 + p), ref=ref)
+        for (name, q), (mode, M, s) in kept.items():
+            if q == p:
+                errs[(name, p)] = (oracle.rel_err(M, s, *ref), tol_mode(mode, floor))
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": f"FP64 oracle binary exponentiation at N={n}, p in (64, 1000); {spent:.1f} s"}
+    return cpu, errs
 
 
 def batched_workload(args):
@@ -199,13 +249,26 @@ def batched_workload(args):
                      "pct_fp32_mfma_peak": round(flop / ms / 1e6 / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2)}
     mpow.mpow_plan_destroy(hb)
     mpow.mpow_plan_destroy(hp)
-    print(json.dumps({"workload": "ragged batch: 4096 FP32 matrices, N in {16..256} step 16, "
-                                  "p log-uniform [2,1000], one persistent graph-replayed launch",
-                      "effective_gflop_per_batch": round(flop / 1e9, 2), "results": res,
-                      "tile_table": {"tuned": tuned_table[1:], "default": default_table[1:],
-                                     "tune_seconds": round(tune_s, 2)},
-                      "speedup_vs_loop": round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)}),
-          flush=True)
+    batched()  # the tuned batch once more: its results for the error sample
+    torch.cuda.synchronize(dev)
+    rng = np.random.default_rng(1)
+    kept = {}
+    for i in sorted(int(x) for x in rng.choice(count, 32, replace=False)):
+        n = nl[i]
+        kept[i] = (host[offs[i]:offs[i] + n * n].reshape(n, n), pl[i],
+                   out[offs[i]:offs[i] + n * n].cpu().numpy().reshape(n, n), float(sc[i].item()))
+    result = {"workload": "ragged batch: 4096 FP32 matrices, N in {16..256} step 16, "
+                          "p log-uniform [2,1000], one persistent graph-replayed launch",
+              "effective_gflop_per_batch": round(flop / 1e9, 2), "results": res,
+              "tile_table": {"tuned": tuned_table[1:], "default": default_table[1:],
+                             "tune_seconds": round(tune_s, 2)},
+              "speedup_vs_loop": round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)}
+    if not args.no_cpu_baseline:
+        cpu, errs = sample_oracle_leg({i: (A, p, 0, M, s) for i, (A, p, M, s) in kept.items()})
+        result["sample_errors"] = errs
+        result["sample_within_tol"] = all(e["within_tol"] for e in errs)
+        result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
     return 0
 
 
@@ -218,7 +281,6 @@ def serving_workload(args):
     import numpy as np
     import torch
 
-    import oracle
     from paper_1204_3052_amd import inputs, mpow
 
     dev = torch.device("cuda:0")
@@ -305,12 +367,9 @@ def serving_workload(args):
     for name, mask in (("fp32", modes == mpow.MPOW_FP32), ("bf16x3", modes == mpow.MPOW_BF16X3),
                        ("batched_route", route == 1), ("n_ge_1024", ns >= 1024)):
         by[name] = {"count": int(mask.sum()), "p50_ms": pct(lat[mask], 50), "p99_ms": pct(lat[mask], 99)}
-    errs = []
-    for i in sorted(sample):
-        A = pool[int(ns[i])].cpu().numpy()
-        ref = oracle.mpow_binary(A, int(ps[i]))
-        errs.append({"n": int(ns[i]), "p": int(ps[i]), "mode": "bf16x3" if modes[i] else "fp32",
-                     "rel_err": float(f"{oracle.rel_err(samp_out[i].cpu().numpy(), float(samp_scale[i].item()), *ref):.3e}")})
+    kept = {i: (pool[int(ns[i])].cpu().numpy(), int(ps[i]), int(modes[i]),
+                samp_out[i].cpu().numpy(), float(samp_scale[i].item())) for i in sorted(sample)}
+    cpu, errs = sample_oracle_leg(kept)
     print(json.dumps({
         "workload": f"serving: Poisson {rate:.0f} req/s for {args.duration:.0f} s, N log-uniform [32,2048] "
                     "step 16, p log-uniform [2,2^20], 50% FP32 / 50% BF16X3",
@@ -322,8 +381,34 @@ def serving_workload(args):
         "span_s": round(span, 3), "wall_s": round(wall, 3), "backpressure_waits": backpressure,
         "arena_peak_bytes": int(stats["arena_peak"]), "arena_budget_bytes": budget,
         "plain_fifo_baseline": fifo,
-        "sample_errors": errs}), flush=True)
+        "sample_errors": errs, "sample_within_tol": all(e["within_tol"] for e in errs),
+        "cpu_baseline": cpu}), flush=True)
     return 0
+
+
+def sample_oracle_leg(kept):
+    """The oracle beside the batched and serving runs: the FP64 oracle on the
+    sampled matrices (timed: cpu_baseline), each sampled result's error
+    against it and its stated tolerance (floor from one perturbed oracle
+    run).  kept[i] = (A, p, mode, M, s)."""
+    import oracle
+    from oracle.tolerance import tol_mode
+    from paper_1204_3052_amd import inputs
+
+    flop, spent, errs = 0.0, 0.0, []
+    for i, (A, p, mode, M, s) in kept.items():
+        n = A.shape[0]
+        t = time.perf_counter()
+        ref = oracle.mpow_binary(A, p)
+        spent += time.perf_counter() - t
+        flop += gemm_count(p) * 2.0 * n ** 3
+        err = oracle.rel_err(M, s, *ref)
+        tol = tol_mode(mode, oracle.floor_estimate(A, p, inputs.relative_signs(n, 3000 + i), ref=ref))
+        errs.append({"n": n, "p": p, "mode": "bf16x3" if mode else "fp32", "rel_err": float(f"{err:.3e}"),
+                     "tol": float(f"{tol:.3e}"), "within_tol": err <= tol})
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": f"FP64 oracle binary exponentiation on {len(kept)} sampled matrices; {spent:.1f} s"}
+    return cpu, errs
 
 
 def fifo_plain_baseline(t_arr, ns, ps, modes, pool, out, scale, flop):
@@ -395,6 +480,19 @@ PAPER_TIMES = {
 }
 
 
+def sequential_product_seconds(A_np) -> float:
+    """The oracle beside the paper's table: one FP64 three-loop product on one
+    host thread (the paper's sequential CPU method), timed."""
+    import numpy as np
+
+    import oracle
+    oracle.set_naive_threads(1)
+    X = A_np.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.matmul_naive(X, X)
+    return time.perf_counter() - t0
+
+
 def paper_workload(args):
     """The paper's table shapes: the logarithmic schedule (mpow_run) against
     the naive p - 1 chained products on the same GPU (mpow_run_naive) and the
@@ -403,7 +501,6 @@ def paper_workload(args):
     import numpy as np
     import torch
 
-    import oracle
     from paper_1204_3052_amd import inputs, mpow
 
     dev = torch.device("cuda:0")
@@ -431,11 +528,7 @@ def paper_workload(args):
                 times.append(e0.elapsed_time(e1))
             res[name] = float(np.median(times)) / 1e3
         if n not in cpu_product_s:
-            oracle.set_naive_threads(1)
-            X = A_np.astype(np.float64)
-            t0 = time.perf_counter()
-            oracle.matmul_naive(X, X)
-            cpu_product_s[n] = time.perf_counter() - t0
+            cpu_product_s[n] = sequential_product_seconds(A_np)
         cpu_s = cpu_product_s[n] * (p - 1)
         rows.append({"n": n, "p": p, "ours_s": round(res["ours"], 6), "naive_gpu_s": round(res["naive_gpu"], 6),
                      "ours_vs_naive_gpu": round(res["naive_gpu"] / res["ours"], 1),
@@ -454,8 +547,8 @@ def paper_workload(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched", "serving", "paper"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
@@ -519,8 +612,10 @@ def main():
         step()
     torch.cuda.synchronize(dev)
 
-    # per-case timing outside the timed region (context only)
+    # per-case timing outside the timed region (context only); the results of
+    # the sizes the oracle leg can reach are kept for its error check
     per_case = []
+    kept = {}
     for i, (n, p) in enumerate(cases):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -531,6 +626,8 @@ def main():
         ms = e0.elapsed_time(e1)
         per_case.append({"n": n, "p": p, "gemms": gemm_count(p), "ms": round(ms, 4),
                          "gflops": round(gemm_count(p) * 2.0 * n ** 3 / ms / 1e6, 1)})
+        if n <= 2048:
+            kept[(n, p)] = (outs[n].cpu().numpy(), float(scales[i].item()))
 
     mpow.mpow_plan_timing_reset(plan)
     torch.cuda.synchronize(dev)
@@ -574,7 +671,14 @@ def main():
         "per_case": per_case,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline()
+        cpu, errs = oracle_leg(cases, kept)
+        result["cpu_baseline"] = cpu
+        for c in per_case:
+            e = errs.get((c["n"], c["p"]))
+            c["rel_err"] = float(f"{e[0]:.3e}") if e else None
+            c["tol"] = float(f"{e[1]:.3e}") if e else None
+        result["errors_checked"] = f"{len(errs)} of {len(per_case)} cases (oracle leg's time budget)"
+        result["errors_within_tol"] = all(e[0] <= e[1] for e in errs.values())
     print(json.dumps(result), flush=True)
     return 0
 

@@ -1,11 +1,9 @@
 """Helpers for GPU tests: run the library through its C ABI on numpy inputs.
 
-Tolerance (float32 products): a result passes when its relative Frobenius
-error against the FP64 oracle is at most max(1e-5, 64 * floor), where floor is
-the oracle's own relative change when every input entry moves by a random
-relative +-2^-24 (the problem's sensitivity to float32-sized input noise).
-At large p the power is ill-conditioned and no float32 method can reach 1e-5;
-the floor term then takes over.
+Tolerances are the stated bars of oracle/tolerance.py: a result passes when
+its relative Frobenius error against the FP64 oracle is at most
+max(ABS, FACTOR * floor), floor being the oracle's own sensitivity to
+float32-sized input noise.
 """
 from __future__ import annotations
 
@@ -14,22 +12,8 @@ import numpy as np
 import oracle
 from paper_1204_3052_amd import inputs, mpow
 
-FP32_ABS_TOL = 1e-5
-FP32_FLOOR_FACTOR = 64.0
-# BF16 hi/lo halves carry about 16 bits of each operand: a looser stated bound.
-BF16X3_ABS_TOL = 2e-4
-BF16X3_FLOOR_FACTOR = 1024.0
-
-
-def tol_fp32(floor: float) -> float:
-    return max(FP32_ABS_TOL, FP32_FLOOR_FACTOR * floor)
-
-
-def tol_mode(mode: int, floor: float) -> float:
-    """Stated tolerance per product mode (FP16X3 shares the float32 bound)."""
-    if mode == mpow.MPOW_BF16X3:
-        return max(BF16X3_ABS_TOL, BF16X3_FLOOR_FACTOR * floor)
-    return tol_fp32(floor)
+from oracle.tolerance import (  # noqa: F401  (the stated bars live beside the oracle)
+    BF16X3_ABS_TOL, BF16X3_FLOOR_FACTOR, FP32_ABS_TOL, FP32_FLOOR_FACTOR, tol_fp32, tol_mode)
 
 
 def run_gpu(plan_handle: int, A_np: np.ndarray, p: int, log_scale: bool = True, out_is_input=False):

@@ -96,3 +96,11 @@ def test_plan_create_without_gpu_reports_device_error(lib):
     h = ctypes.c_void_p()
     st = lib.mpow_plan_create(ctypes.byref(h), 0, 64, 0, 0, 0)
     assert st == mpow.MPOW_ERR_DEVICE and not h.value
+
+
+def test_tolerance_modes_match_library():
+    from oracle import tolerance
+    assert (tolerance.MODE_FP32, tolerance.MODE_FP16X3, tolerance.MODE_BF16X3) == \
+        (mpow.MPOW_FP32, mpow.MPOW_FP16X3, mpow.MPOW_BF16X3)
+    assert tolerance.tol_fp32(0.0) == 1e-5 and tolerance.tol_fp32(1e-3) == 64e-3
+    assert tolerance.tol_mode(mpow.MPOW_BF16X3, 0.0) == 2e-4
