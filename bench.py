@@ -95,9 +95,9 @@ def oracle_leg(cases, results, seconds_budget: float = 20.0):
 
 
 def split_workload(args):
-    """FP32 vs the two split-precision modes on N=4096, p in {64, 1000}.
-    Same effective-flop formula for every mode (G(p) 2N^3); the split modes
-    also report their MFMA rate (three 16-bit products per product) against
+    """FP32 vs the split-precision modes on N=4096, p in {64, 1000}.  Same
+    effective-flop formula for every mode (G(p) 2N^3); the split modes also
+    report their MFMA rate (three or six 16-bit products per product) against
     the FP16/BF16 dense peak.  The oracle leg then reports each result's
     relative Frobenius error against the FP64 oracle beside its stated
     tolerance, and the oracle's own rate."""
@@ -115,7 +115,8 @@ def split_workload(args):
     sc = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     rows, kept = [], {}
-    modes = (("fp32", mpow.MPOW_FP32), ("fp16x3", mpow.MPOW_FP16X3), ("bf16x3", mpow.MPOW_BF16X3))
+    modes = (("fp32", mpow.MPOW_FP32), ("fp16x3", mpow.MPOW_FP16X3), ("bf16x3", mpow.MPOW_BF16X3),
+             ("bf16x6", mpow.MPOW_BF16X6))
     for name, mode in modes:
         plan = mpow.mpow_plan_create(0, n, 0, mode, 0)
         for p in (64, 1000):
@@ -138,7 +139,8 @@ def split_workload(args):
                    "gflops": round(gflops, 1),
                    "pct_fp32_mfma_peak": round(gflops / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2)}
             if mode != mpow.MPOW_FP32:
-                row["mfma_pct_of_16bit_peak"] = round(3 * gflops / (MFMA_16BIT_PEAK_TFLOPS * 1e3) * 100, 2)
+                products = 6 if mode == mpow.MPOW_BF16X6 else 3
+                row["mfma_pct_of_16bit_peak"] = round(products * gflops / (MFMA_16BIT_PEAK_TFLOPS * 1e3) * 100, 2)
             rows.append(row)
             kept[(name, p)] = (mode, out.cpu().numpy(), float(sc.item()))
         mpow.mpow_plan_destroy(plan)

@@ -58,11 +58,17 @@ typedef enum mpow_status {
  *              three FP16 MFMA products accumulated in float32 (about
  *              float32 accuracy).
  *  MPOW_BF16X3 the same with BF16 halves (about 16 bits of operand
- *              precision; looser tolerance). */
+ *              precision; looser tolerance).
+ *  MPOW_BF16X6 X' split into three BF16 parts x0 + x1 + x2 (about 24 bits);
+ *              a product is the six BF16 MFMA products x_i y_j with
+ *              i + j <= 2, accumulated in float32 (float32-level accuracy
+ *              with float32's exponent range, after Henry, Tang and
+ *              Heinecke, ARITH 2019). */
 typedef enum mpow_mode {
     MPOW_FP32 = 0,
     MPOW_FP16X3 = 1,
-    MPOW_BF16X3 = 2
+    MPOW_BF16X3 = 2,
+    MPOW_BF16X6 = 3
 } mpow_mode;
 
 /* Plan flags. */
@@ -202,6 +208,8 @@ enum {
     MPOW_KERNEL_GEMM_F32_32_K8 = 10, /* float32 product, 32x32 tiles, K split over 8 waves */
     MPOW_KERNEL_GEMM_F32_64_K2 = 11, /* float32 product, 64x64 tiles, 2x2 waves, K split in 2 */
     MPOW_KERNEL_GEMM_F32_128_K2 = 12, /* float32 product, 128x128 tiles, 2x2 waves, K split in 2 */
+    MPOW_KERNEL_GEMM_BF16X6_128 = 13, /* BF16 three-part six-product, 128x128 tiles */
+    MPOW_KERNEL_GEMM_BF16X6_256 = 14, /* BF16 three-part six-product, 256x256 tiles, 8 waves */
     MPOW_KERNEL_COUNT = 16
 };
 

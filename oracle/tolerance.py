@@ -8,7 +8,8 @@ problem's sensitivity to float32-sized input noise; floor_estimate).  At
 large p the power is ill-conditioned and no float32 method can reach the
 absolute bar; the floor term then takes over.
 
-  float32 products and FP16 hi/lo (3 products): ABS 1e-5,  FACTOR 64
+  float32 products, FP16 hi/lo (3 products) and
+  BF16 three parts (6 products):                 ABS 1e-5,  FACTOR 64
   BF16 hi/lo (3 products, about 16 bits each):  ABS 2e-4,  FACTOR 1024
 """
 FP32_ABS_TOL = 1e-5
@@ -17,7 +18,7 @@ BF16X3_ABS_TOL = 2e-4
 BF16X3_FLOOR_FACTOR = 1024.0
 
 # product modes, as numbered by the library's C interface
-MODE_FP32, MODE_FP16X3, MODE_BF16X3 = 0, 1, 2
+MODE_FP32, MODE_FP16X3, MODE_BF16X3, MODE_BF16X6 = 0, 1, 2, 3
 
 
 def tol_fp32(floor: float) -> float:
@@ -25,7 +26,8 @@ def tol_fp32(floor: float) -> float:
 
 
 def tol_mode(mode: int, floor: float) -> float:
-    """Stated tolerance per product mode (FP16X3 shares the float32 bound)."""
+    """Stated tolerance per product mode (FP16X3 and BF16X6 share the float32
+    bound)."""
     if mode == MODE_BF16X3:
         return max(BF16X3_ABS_TOL, BF16X3_FLOOR_FACTOR * floor)
     return tol_fp32(floor)

@@ -75,7 +75,7 @@ int mpow_schedule(int64_t p, uint8_t *ops, int cap) {
 }
 
 size_t mpow_workspace_bytes(int max_n, int max_batch, int mode) {
-    if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X3) return 0;
+    if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X6) return 0;
     size_t total = workspace_bytes(max_n, mode);
     if (max_batch > 0) total += batch_device_bytes(max_batch, batch_bmax(max_n), kWorkersForSizing);
     return total;
@@ -85,7 +85,7 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
                              int mode, uint32_t flags) {
     if (!out_plan) return MPOW_ERR_INVALID;
     *out_plan = nullptr;
-    if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X3 ||
+    if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X6 ||
         (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON)) != 0)
         return MPOW_ERR_INVALID;
     int ndev = 0;
@@ -224,10 +224,7 @@ mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel) {
     if (!plan) return MPOW_ERR_INVALID;
     bool ok = kernel == -1;
     if (!ok && plan->mode == MPOW_FP32) ok = gemm_is_f32(kernel);
-    if (!ok && plan->mode == MPOW_FP16X3)
-        ok = kernel == MPOW_KERNEL_GEMM_F16X3_128 || kernel == MPOW_KERNEL_GEMM_F16X3_256;
-    if (!ok && plan->mode == MPOW_BF16X3)
-        ok = kernel == MPOW_KERNEL_GEMM_BF16X3_128 || kernel == MPOW_KERNEL_GEMM_BF16X3_256;
+    if (!ok && plan->mode != MPOW_FP32) ok = gemm_split_mode(kernel) == plan->mode;
     if (!ok) return MPOW_ERR_INVALID;
     plan->ws.kernel = kernel;
     return MPOW_SUCCESS;

@@ -26,8 +26,10 @@ struct Workspace {
     double *part[2] = {nullptr, nullptr};
     double *partA = nullptr;
     int *escale = nullptr;
-    void *sx[4] = {nullptr, nullptr, nullptr, nullptr};
-    void *sa[4] = {nullptr, nullptr, nullptr, nullptr};
+    // split parts of the running matrix (sx) and of A (sa): [0] row-major,
+    // [1] transposed, part k = 0 .. split_parts(mode) - 1
+    void *sx[2][3] = {};
+    void *sa[2][3] = {};
     int max_n = 0;
     int mode = MPOW_FP32;
     int kernel = -1;  // product kernel forced for every size, -1: per-size default
@@ -92,19 +94,21 @@ struct SplitLaunch {
     const double *part;   // partial sums of squares of X
     int nPart;
     int n, ld;
-    void *hi, *lo, *hiT, *loT;
+    void *rm[3], *tr[3];  // parts, row-major and transposed (ld x ld each)
     int *eSlot;           // block (0,0) records e of X here (may be null)
 };
 
-// Split-precision product: C = (X'Y') * 2^-2k from the hi/lo halves.
+// Split-precision product: C = (X'Y') * 2^-2k from the operands' parts.
 struct SplitGemmLaunch {
-    const void *xh, *xl;  // left operand, row-major, ld
-    const void *yh, *yl;  // right operand, transposed, ld
+    const void *x[3];  // left operand's parts, row-major, ld
+    const void *y[3];  // right operand's parts, transposed, ld
     float *C;
     double *partC;
     int n, ld;
 };
 
+int split_parts(int mode);  // 16-bit parts per operand (0 for MPOW_FP32)
+int gemm_split_mode(int kernel);  // the mode of a split kernel id, -1 if none
 int split_ld(int n);
 hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s);
 int gemm_split_pick(int mode, int n);

@@ -26,7 +26,8 @@ Layout layout_for(int max_n, int mode) {
     z.escale = round_up((MPOW_NAIVE_MAX_P + 2) * sizeof(int), 256);
     const size_t ld = (size_t)split_ld(max_n);
     z.split = mode == MPOW_FP32 ? 0 : round_up(ld * ld * 2, 256);
-    z.total = 2 * z.buf + 2 * z.part + z.partA + z.escale + 8 * z.split;
+    // two operands (running matrix, A) x two layouts x the mode's parts
+    z.total = 2 * z.buf + 2 * z.part + z.partA + z.escale + 4 * split_parts(mode) * z.split;
     return z;
 }
 
@@ -43,10 +44,11 @@ void workspace_carve(char *base, int max_n, int mode, Workspace *ws) {
     ws->part[1] = (double *)q; q += z.part;
     ws->partA = (double *)q; q += z.partA;
     ws->escale = (int *)q; q += z.escale;
-    for (int k = 0; k < 4; ++k) {
-        ws->sx[k] = z.split ? (void *)q : nullptr; q += z.split;
-        ws->sa[k] = z.split ? (void *)q : nullptr; q += z.split;
-    }
+    for (int l = 0; l < 2; ++l)
+        for (int k = 0; k < split_parts(mode); ++k) {
+            ws->sx[l][k] = (void *)q; q += z.split;
+            ws->sa[l][k] = (void *)q; q += z.split;
+        }
     ws->max_n = max_n;
     ws->mode = mode;
 }
@@ -186,27 +188,28 @@ hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, cons
     const int kernel = ws.kernel >= 0 ? ws.kernel : gemm_split_pick(mode, n);
     const int tiles = gemm_split_tiles(kernel, n);
 
-    SplitLaunch sl;
+    const int np = split_parts(mode);
+    SplitLaunch sl{};
     sl.X = A;
     sl.part = ws.partA;
     sl.nPart = nbA;
     sl.n = n;
     sl.ld = ld;
-    sl.hi = ws.sa[0];
-    sl.lo = ws.sa[1];
-    sl.hiT = ws.sa[2];
-    sl.loT = ws.sa[3];
+    for (int k = 0; k < np; ++k) {
+        sl.rm[k] = ws.sa[0][k];
+        sl.tr[k] = ws.sa[1][k];
+    }
     sl.eSlot = ws.escale;
     MPOW_TRY(launch_split(mode, sl, s));
 
     for (int k = 1; k <= G; ++k) {
-        void *const *xs = (k == 1) ? ws.sa : ws.sx;
-        void *const *ys = (ops[k - 1] == 0) ? xs : ws.sa;
-        SplitGemmLaunch g;
-        g.xh = xs[0];
-        g.xl = xs[1];
-        g.yh = ys[2];
-        g.yl = ys[3];
+        void *const(*xs)[3] = (k == 1) ? ws.sa : ws.sx;
+        void *const(*ys)[3] = (ops[k - 1] == 0) ? xs : ws.sa;
+        SplitGemmLaunch g{};
+        for (int q = 0; q < np; ++q) {
+            g.x[q] = xs[0][q];
+            g.y[q] = ys[1][q];
+        }
         g.C = ws.buf[k & 1];
         g.partC = ws.part[k & 1];
         g.n = n;
@@ -219,10 +222,10 @@ hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, cons
             sl.X = g.C;
             sl.part = g.partC;
             sl.nPart = tiles;
-            sl.hi = ws.sx[0];
-            sl.lo = ws.sx[1];
-            sl.hiT = ws.sx[2];
-            sl.loT = ws.sx[3];
+            for (int q = 0; q < np; ++q) {
+                sl.rm[q] = ws.sx[0][q];
+                sl.tr[q] = ws.sx[1][q];
+            }
             sl.eSlot = ws.escale + k;
             MPOW_TRY(launch_split(mode, sl, s));
         }

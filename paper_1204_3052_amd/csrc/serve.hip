@@ -277,7 +277,7 @@ mpow_status mpow_srv_create(mpow_srv_t *out_srv, int device, int max_n, size_t h
 
 mpow_status mpow_srv_submit(mpow_srv_t srv, const float *A, int n, int64_t p, int mode, float *out,
                             double *log2_scale, uint64_t *id) {
-    if (!srv || !A || !out || n < 1 || n > srv->max_n || p < 0 || mode < 0 || mode > MPOW_BF16X3)
+    if (!srv || !A || !out || n < 1 || n > srv->max_n || p < 0 || mode < 0 || mode > MPOW_BF16X6)
         return MPOW_ERR_INVALID;
     if (((uintptr_t)A & 3) || ((uintptr_t)out & 3) || ((uintptr_t)log2_scale & 7))
         return MPOW_ERR_INVALID;
@@ -387,7 +387,7 @@ mpow_status mpow_srv_simulate(const mpow_sim_config *cfg, const mpow_sim_request
         !(cfg->batch_flops > 0) || cfg->launch_overhead_s < 0)
         return MPOW_ERR_INVALID;
     for (int i = 0; i < count; ++i)
-        if (reqs[i].n < 1 || reqs[i].p < 0 || reqs[i].mode < 0 || reqs[i].mode > MPOW_BF16X3 ||
+        if (reqs[i].n < 1 || reqs[i].p < 0 || reqs[i].mode < 0 || reqs[i].mode > MPOW_BF16X6 ||
             (i > 0 && reqs[i].t_arrive < reqs[i - 1].t_arrive))
             return MPOW_ERR_INVALID;
 

@@ -1,24 +1,29 @@
-// Split-precision products (modes FP16X3 and BF16X3).
+// Split-precision products (modes FP16X3, BF16X3 and BF16X6).
 //
-// Every float32 operand X is written as two 16-bit matrices,
+// Every float32 operand X is written as NP 16-bit matrices,
 //   X' = X * 2^(k - e)          (e = floor(log2 ||X||_F), k a fixed shift)
-//   hi = rn16(X'),  lo = rn16(X' - hi)
-// so that X' = hi + lo to about 22 bits (FP16) or 16 bits (BF16).  A product
-// then takes three 16-bit MFMA products accumulated in one float32
-// accumulator, dropping the lo*lo term:
-//   X'Y' ~= hi_X hi_Y + hi_X lo_Y + lo_X hi_Y.
-// For FP16 the fixed shift k = 14 puts the largest entry of a normalised
-// matrix (||X'||_F < 2^15) inside FP16 range and keeps typical entries, and
-// their lo parts, well above FP16's subnormals (an entry of size 2^-12, the
-// typical one of a normalised 4096 x 4096 matrix, becomes 4 and its lo part
-// about 2^-10).  BF16 has float32's exponent range and needs no shift.  One
-// accumulator instead of separate hi*hi and cross-term accumulators halves
-// the accumulator registers, which lets two waves share a SIMD.
+//   x0 = rn16(X'),  x1 = rn16(X' - x0),  x2 = rn16(X' - x0 - x1)
+// (each difference is exact in float32), so that X' = x0 + x1 (+ x2) to about
+// 22 bits (FP16, NP = 2), 16 bits (BF16, NP = 2) or 24 bits (BF16, NP = 3).
+// A product then takes the 16-bit MFMA products x_i y_j with i + j < NP
+// (three for NP = 2, six for NP = 3: the terms of order 2^-8 NP and below
+// are dropped), accumulated in one float32 accumulator:
+//   NP = 2:  x0 y0 + x0 y1 + x1 y0
+//   NP = 3:  x0 y0 + x0 y1 + x1 y0 + x0 y2 + x1 y1 + x2 y0
+// The six-product BF16 form is the bfloat16 scheme of Henry, Tang and
+// Heinecke (ARITH 2019): float32-level products that keep float32's exponent
+// range.  For FP16 the fixed shift k = 14 puts the largest entry of a
+// normalised matrix (||X'||_F < 2^15) inside FP16 range and keeps typical
+// entries, and their second parts, well above FP16's subnormals (an entry of
+// size 2^-12, the typical one of a normalised 4096 x 4096 matrix, becomes 4
+// and its second part about 2^-10).  BF16 has float32's exponent range and
+// needs no shift.  One accumulator instead of one per order of magnitude
+// halves the accumulator registers, which lets two waves share a SIMD.
 //
-// split_kernel turns a float32 matrix into hi/lo in two layouts: row-major
-// (the left operand: a lane reads 8 consecutive k of its row) and transposed
-// (the right operand: row j holds column j, so a lane again reads 8
-// consecutive k).  Both are zero-padded to ld = n rounded up to 256, so the
+// split_kernel turns a float32 matrix into its parts in two layouts:
+// row-major (the left operand: a lane reads 8 consecutive k of its row) and
+// transposed (the right operand: row j holds column j, so a lane again reads
+// 8 consecutive k).  Both are zero-padded to ld = n rounded up to 256, so the
 // product kernel's loads need no bounds checks.
 #include "mpow_internal.h"
 #include "scale_device.h"
@@ -43,7 +48,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
 struct Vec8;
@@ -71,13 +75,12 @@ __device__ __forceinline__ v16f mfma16<__bf16>(b8 a, b8 b, v16f c) {
 
 constexpr int STS = 64;  // split tile edge
 
-template <typename T>
+template <typename T, int NP>
 __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
     typedef SplitTraits<T> Tr;
     typedef T V4 __attribute__((ext_vector_type(4)));
     __shared__ double red[256];
-    __shared__ T th[STS][STS + 8];
-    __shared__ T tl[STS][STS + 8];
+    __shared__ T tp[NP][STS][STS + 8];  // the parts of the tile, for the transpose
     const int tid = threadIdx.x;
     const int n = s.n, ld = s.ld;
     const int eX = exponent_of_sumsq(block_sum_partials<256>(s.part, s.nPart, red));
@@ -101,33 +104,33 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
                     if (gc + t < n) v[t] = s.X[(int64_t)gr * n + gc + t];
             }
         }
-        V4 hv, lv;
+        V4 pv[NP];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const float x = v[t] * f.a * f.b;
-            const T h = (T)x;
-            const T l = (T)(x - (float)h);
-            hv[t] = h;
-            lv[t] = l;
-            th[r][c + t] = h;
-            tl[r][c + t] = l;
+            float x = v[t] * f.a * f.b;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const T h = (T)x;
+                pv[k][t] = h;
+                tp[k][r][c + t] = h;
+                x = x - (float)h;  // exact: the rest of x after the first k + 1 parts
+            }
         }
         // four 16-bit values per 8-byte store (ld and gc are multiples of 4)
-        *(V4 *)((T *)s.hi + (int64_t)gr * ld + gc) = hv;
-        *(V4 *)((T *)s.lo + (int64_t)gr * ld + gc) = lv;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) *(V4 *)((T *)s.rm[k] + (int64_t)gr * ld + gc) = pv[k];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int c = tid / 16 + 16 * q, r = (tid % 16) * 4;
-        V4 hv, lv;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            hv[t] = th[r + t][c];
-            lv[t] = tl[r + t][c];
+        for (int k = 0; k < NP; ++k) {
+            V4 hv;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) hv[t] = tp[k][r + t][c];
+            *(V4 *)((T *)s.tr[k] + (int64_t)(c0 + c) * ld + r0 + r) = hv;
         }
-        *(V4 *)((T *)s.hiT + (int64_t)(c0 + c) * ld + r0 + r) = hv;
-        *(V4 *)((T *)s.loT + (int64_t)(c0 + c) * ld + r0 + r) = lv;
     }
 }
 
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
 
 // SBK is the K extent (16-bit elements) of one LDS tile; rows are padded by 8
 // elements so that 16-byte LDS reads are conflict-free.
-template <typename T, int BM, int BN, int WM, int WN, int SBK>
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK>
 __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch g) {
     typedef SplitTraits<T> Tr;
     typedef typename Vec8<T>::type V8;
@@ -144,10 +147,8 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 32, FN = TN / 32;
 
-    __shared__ __attribute__((aligned(16))) T Ah[2][BM * SLD];
-    __shared__ __attribute__((aligned(16))) T Al[2][BM * SLD];
-    __shared__ __attribute__((aligned(16))) T Bh[2][BN * SLD];
-    __shared__ __attribute__((aligned(16))) T Bl[2][BN * SLD];
+    __shared__ __attribute__((aligned(16))) T As[NP][2][BM * SLD];
+    __shared__ __attribute__((aligned(16))) T Bs[NP][2][BN * SLD];
     __shared__ double red[WM * WN];
 
     const int n = g.n, ld = g.ld;
@@ -165,44 +166,40 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     constexpr int LA = BM * CPR / NT;
     constexpr int LB = BN * CPR / NT;
     static_assert(LA * NT == BM * CPR && LB * NT == BN * CPR, "load split");
-    u4 rah[LA], ral[LA], rbh[LB], rbl[LB];
-    const T *__restrict__ xh = (const T *)g.xh;
-    const T *__restrict__ xl = (const T *)g.xl;
-    const T *__restrict__ yh = (const T *)g.yh;
-    const T *__restrict__ yl = (const T *)g.yl;
+    u4 ra[NP][LA], rb[NP][LB];
 
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int r = 0; r < LA; ++r) {
-            const int idx = tid + r * NT;
-            const int row = idx / CPR, c = (idx % CPR) * 8;
-            const int64_t off = (int64_t)(m0 + row) * ld + k0 + c;
-            rah[r] = *(const u4 *)(xh + off);
-            ral[r] = *(const u4 *)(xl + off);
-        }
+        for (int k = 0; k < NP; ++k) {
 #pragma unroll
-        for (int r = 0; r < LB; ++r) {
-            const int idx = tid + r * NT;
-            const int row = idx / CPR, c = (idx % CPR) * 8;
-            const int64_t off = (int64_t)(n0 + row) * ld + k0 + c;
-            rbh[r] = *(const u4 *)(yh + off);
-            rbl[r] = *(const u4 *)(yl + off);
+            for (int r = 0; r < LA; ++r) {
+                const int idx = tid + r * NT;
+                const int row = idx / CPR, c = (idx % CPR) * 8;
+                ra[k][r] = *(const u4 *)((const T *)g.x[k] + (int64_t)(m0 + row) * ld + k0 + c);
+            }
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                const int idx = tid + r * NT;
+                const int row = idx / CPR, c = (idx % CPR) * 8;
+                rb[k][r] = *(const u4 *)((const T *)g.y[k] + (int64_t)(n0 + row) * ld + k0 + c);
+            }
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int r = 0; r < LA; ++r) {
-            const int idx = tid + r * NT;
-            const int row = idx / CPR, c = (idx % CPR) * 8;
-            *(u4 *)(&Ah[buf][row * SLD + c]) = rah[r];
-            *(u4 *)(&Al[buf][row * SLD + c]) = ral[r];
-        }
+        for (int k = 0; k < NP; ++k) {
 #pragma unroll
-        for (int r = 0; r < LB; ++r) {
-            const int idx = tid + r * NT;
-            const int row = idx / CPR, c = (idx % CPR) * 8;
-            *(u4 *)(&Bh[buf][row * SLD + c]) = rbh[r];
-            *(u4 *)(&Bl[buf][row * SLD + c]) = rbl[r];
+            for (int r = 0; r < LA; ++r) {
+                const int idx = tid + r * NT;
+                const int row = idx / CPR, c = (idx % CPR) * 8;
+                *(u4 *)(&As[k][buf][row * SLD + c]) = ra[k][r];
+            }
+#pragma unroll
+            for (int r = 0; r < LB; ++r) {
+                const int idx = tid + r * NT;
+                const int row = idx / CPR, c = (idx % CPR) * 8;
+                *(u4 *)(&Bs[k][buf][row * SLD + c]) = rb[k][r];
+            }
         }
     };
 
@@ -224,32 +221,28 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
         if (kt + 1 < nk) gload((kt + 1) * SBK);
 #pragma unroll
         for (int s = 0; s < SBK / 16; ++s) {
-            V8 ah[FM], al[FM], bh[FN], bl[FN];
+            V8 a[NP][FM], b[NP][FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                const int off = (wm * TM + i * 32 + l32) * SLD + s * 16 + grp * 8;
-                ah[i] = *(const V8 *)(&Ah[cur][off]);
-                al[i] = *(const V8 *)(&Al[cur][off]);
+            for (int k = 0; k < NP; ++k) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    a[k][i] = *(const V8 *)(&As[k][cur][(wm * TM + i * 32 + l32) * SLD + s * 16 + grp * 8]);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b[k][j] = *(const V8 *)(&Bs[k][cur][(wn * TN + j * 32 + l32) * SLD + s * 16 + grp * 8]);
             }
+            // per accumulator, in this fixed order: the products x_u y_v
+            // grouped by d = u + v = 0, 1, ..., NP - 1, u ascending within a
+            // group: x0y0, x0y1, x1y0 (, x0y2, x1y1, x2y0)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const int off = (wn * TN + j * 32 + l32) * SLD + s * 16 + grp * 8;
-                bh[j] = *(const V8 *)(&Bh[cur][off]);
-                bl[j] = *(const V8 *)(&Bl[cur][off]);
-            }
-            // per accumulator: hi.hi, then hi.lo, then lo.hi (fixed order)
+            for (int d = 0; d < NP; ++d)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int u = 0; u <= d; ++u)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<T>(ah[i], bh[j], acc[i][j]);
+                    for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<T>(ah[i], bl[j], acc[i][j]);
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j) acc[i][j] = mfma16<T>(al[i], bh[j], acc[i][j]);
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = mfma16<T>(a[u][i], b[d - u][j], acc[i][j]);
         }
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
@@ -284,43 +277,65 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     }
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int SBK>
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK>
 hipError_t launch_gemm_split(const SplitGemmLaunch &g, hipStream_t s) {
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_split_kernel<T, BM, BN, WM, WN, SBK>), dim3(tiles), dim3(WM * WN * 64),
-                       0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<T, NP, BM, BN, WM, WN, SBK>), dim3(tiles),
+                       dim3(WM * WN * 64), 0, s, g);
     return hipGetLastError();
 }
 
 }  // namespace
+
+int split_parts(int mode) { return mode == MPOW_BF16X6 ? 3 : (mode == MPOW_FP32 ? 0 : 2); }
 
 // Padded leading dimension of the split operands: a multiple of the largest
 // product tile, so tiles read zeros past n and need no bounds checks.
 int split_ld(int n) { return (n + 255) / 256 * 256; }
 
 hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
-    const int t = sl.ld / STS;
+    const dim3 grid(sl.ld / STS, sl.ld / STS);
     if (mode == MPOW_FP16X3)
-        hipLaunchKernelGGL(split_kernel<_Float16>, dim3(t, t), dim3(256), 0, s, sl);
+        hipLaunchKernelGGL((split_kernel<_Float16, 2>), grid, dim3(256), 0, s, sl);
+    else if (mode == MPOW_BF16X3)
+        hipLaunchKernelGGL((split_kernel<__bf16, 2>), grid, dim3(256), 0, s, sl);
+    else if (mode == MPOW_BF16X6)
+        hipLaunchKernelGGL((split_kernel<__bf16, 3>), grid, dim3(256), 0, s, sl);
     else
-        hipLaunchKernelGGL(split_kernel<__bf16>, dim3(t, t), dim3(256), 0, s, sl);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 // 256 x 256 tiles (8 waves, each 128 x 64, K tile 16) from this size up:
 // twice the MFMA work per LDS byte of the 128 x 128 tile.  Both accumulate
-// every output in the same order (per 16-wide K chunk: hi.hi, hi.lo, lo.hi),
-// so the two give bit-identical results.
+// every output in the same order (per 16-wide K chunk, the fixed product
+// order above), so the two give bit-identical results.
 constexpr int kSplit256From = 2048;
 
 int gemm_split_pick(int mode, int n) {
     const bool big = n >= kSplit256From;
     if (mode == MPOW_FP16X3) return big ? MPOW_KERNEL_GEMM_F16X3_256 : MPOW_KERNEL_GEMM_F16X3_128;
+    if (mode == MPOW_BF16X6) return big ? MPOW_KERNEL_GEMM_BF16X6_256 : MPOW_KERNEL_GEMM_BF16X6_128;
     return big ? MPOW_KERNEL_GEMM_BF16X3_256 : MPOW_KERNEL_GEMM_BF16X3_128;
 }
 
+int gemm_split_mode(int kernel) {
+    switch (kernel) {
+        case MPOW_KERNEL_GEMM_F16X3_128:
+        case MPOW_KERNEL_GEMM_F16X3_256: return MPOW_FP16X3;
+        case MPOW_KERNEL_GEMM_BF16X3_128:
+        case MPOW_KERNEL_GEMM_BF16X3_256: return MPOW_BF16X3;
+        case MPOW_KERNEL_GEMM_BF16X6_128:
+        case MPOW_KERNEL_GEMM_BF16X6_256: return MPOW_BF16X6;
+        default: return -1;
+    }
+}
+
 static int split_tile_edge(int kernel) {
-    return (kernel == MPOW_KERNEL_GEMM_F16X3_256 || kernel == MPOW_KERNEL_GEMM_BF16X3_256) ? 256 : 128;
+    return (kernel == MPOW_KERNEL_GEMM_F16X3_256 || kernel == MPOW_KERNEL_GEMM_BF16X3_256 ||
+            kernel == MPOW_KERNEL_GEMM_BF16X6_256)
+               ? 256
+               : 128;
 }
 
 int gemm_split_tiles(int kernel, int n) {
@@ -331,20 +346,24 @@ int gemm_split_tiles(int kernel, int n) {
 
 const char *gemm_split_name(int kernel) {
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_kernel<_Float16,128,128,2,2,32>";
-        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_kernel<__bf16,128,128,2,2,32>";
-        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_kernel<_Float16,256,256,2,4,16>";
-        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_kernel<__bf16,256,256,2,4,16>";
+        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_kernel<_Float16,2,128,128,2,2,32>";
+        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_kernel<__bf16,2,128,128,2,2,32>";
+        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_kernel<_Float16,2,256,256,2,4,16>";
+        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_kernel<__bf16,2,256,256,2,4,16>";
+        case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_kernel<__bf16,3,128,128,2,2,32>";
+        case MPOW_KERNEL_GEMM_BF16X6_256: return "gemm_split_kernel<__bf16,3,256,256,2,4,16>";
         default: return nullptr;
     }
 }
 
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s) {
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F16X3_128: return launch_gemm_split<_Float16, 128, 128, 2, 2, 32>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X3_128: return launch_gemm_split<__bf16, 128, 128, 2, 2, 32>(g, s);
-        case MPOW_KERNEL_GEMM_F16X3_256: return launch_gemm_split<_Float16, 256, 256, 2, 4, 16>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X3_256: return launch_gemm_split<__bf16, 256, 256, 2, 4, 16>(g, s);
+        case MPOW_KERNEL_GEMM_F16X3_128: return launch_gemm_split<_Float16, 2, 128, 128, 2, 2, 32>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_128: return launch_gemm_split<__bf16, 2, 128, 128, 2, 2, 32>(g, s);
+        case MPOW_KERNEL_GEMM_F16X3_256: return launch_gemm_split<_Float16, 2, 256, 256, 2, 4, 16>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_256: return launch_gemm_split<__bf16, 2, 256, 256, 2, 4, 16>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X6_128: return launch_gemm_split<__bf16, 3, 128, 128, 2, 2, 32>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X6_256: return launch_gemm_split<__bf16, 3, 256, 256, 2, 4, 16>(g, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -25,6 +25,7 @@ MPOW_ERR_TIMEOUT = 6
 MPOW_FP32 = 0
 MPOW_FP16X3 = 1
 MPOW_BF16X3 = 2
+MPOW_BF16X6 = 3
 
 MPOW_FLAG_TIMING = 1
 MPOW_FLAG_POISON = 2
@@ -46,6 +47,8 @@ MPOW_KERNEL_GEMM_F32_32_K4 = 9
 MPOW_KERNEL_GEMM_F32_32_K8 = 10
 MPOW_KERNEL_GEMM_F32_64_K2 = 11
 MPOW_KERNEL_GEMM_F32_128_K2 = 12
+MPOW_KERNEL_GEMM_BF16X6_128 = 13
+MPOW_KERNEL_GEMM_BF16X6_256 = 14
 MPOW_KERNEL_COUNT = 16
 
 # every symbol include/mpow.h declares

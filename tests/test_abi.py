@@ -100,7 +100,8 @@ def test_plan_create_without_gpu_reports_device_error(lib):
 
 def test_tolerance_modes_match_library():
     from oracle import tolerance
-    assert (tolerance.MODE_FP32, tolerance.MODE_FP16X3, tolerance.MODE_BF16X3) == \
-        (mpow.MPOW_FP32, mpow.MPOW_FP16X3, mpow.MPOW_BF16X3)
+    assert (tolerance.MODE_FP32, tolerance.MODE_FP16X3, tolerance.MODE_BF16X3, tolerance.MODE_BF16X6) == \
+        (mpow.MPOW_FP32, mpow.MPOW_FP16X3, mpow.MPOW_BF16X3, mpow.MPOW_BF16X6)
+    assert tolerance.tol_mode(mpow.MPOW_BF16X6, 0.0) == 1e-5
     assert tolerance.tol_fp32(0.0) == 1e-5 and tolerance.tol_fp32(1e-3) == 64e-3
     assert tolerance.tol_mode(mpow.MPOW_BF16X3, 0.0) == 2e-4

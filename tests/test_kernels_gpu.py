@@ -77,6 +77,7 @@ def test_k_split_exact_cases(fplan, kernel):
 @pytest.mark.parametrize("mode,kernels", [
     (mpow.MPOW_FP16X3, [mpow.MPOW_KERNEL_GEMM_F16X3_128, mpow.MPOW_KERNEL_GEMM_F16X3_256]),
     (mpow.MPOW_BF16X3, [mpow.MPOW_KERNEL_GEMM_BF16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256]),
+    (mpow.MPOW_BF16X6, [mpow.MPOW_KERNEL_GEMM_BF16X6_128, mpow.MPOW_KERNEL_GEMM_BF16X6_256]),
 ])
 def test_split_mode_tile_sizes_bit_identical(mode, kernels):
     h = mpow.mpow_plan_create(0, 1100, 0, mode, 0)
@@ -97,14 +98,16 @@ def test_split_mode_tile_sizes_bit_identical(mode, kernels):
 def test_set_kernel_rejects_other_modes():
     h = mpow.mpow_plan_create(0, 64, 0, mpow.MPOW_FP32, 0)
     try:
-        for bad in (-2, mpow.MPOW_KERNEL_GEMM_F16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256, 13, 99):
+        for bad in (-2, mpow.MPOW_KERNEL_GEMM_F16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256,
+                    mpow.MPOW_KERNEL_GEMM_BF16X6_128, 15, 99):
             with pytest.raises(mpow.MpowError):
                 mpow.mpow_plan_set_kernel(h, bad)
     finally:
         mpow.mpow_plan_destroy(h)
     h = mpow.mpow_plan_create(0, 64, 0, mpow.MPOW_FP16X3, 0)
     try:
-        for bad in (mpow.MPOW_KERNEL_GEMM_F32_128, mpow.MPOW_KERNEL_GEMM_BF16X3_128):
+        for bad in (mpow.MPOW_KERNEL_GEMM_F32_128, mpow.MPOW_KERNEL_GEMM_BF16X3_128,
+                    mpow.MPOW_KERNEL_GEMM_BF16X6_128):
             with pytest.raises(mpow.MpowError):
                 mpow.mpow_plan_set_kernel(h, bad)
         mpow.mpow_plan_set_kernel(h, mpow.MPOW_KERNEL_GEMM_F16X3_256)

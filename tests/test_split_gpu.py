@@ -1,7 +1,8 @@
-"""GPU parity of the split-precision modes (FP16X3, BF16X3) against the FP64
-oracle, through the C ABI.  FP16X3 must meet the float32 tolerance; BF16X3 its
-own looser stated tolerance.  0/1 and power-of-two structure is exact in both
-(lo halves are zero), as are small integers."""
+"""GPU parity of the split-precision modes (FP16X3, BF16X3, BF16X6) against
+the FP64 oracle, through the C ABI.  FP16X3 and BF16X6 must meet the float32
+tolerance; BF16X3 its own looser stated tolerance.  0/1 and power-of-two
+structure is exact in all (the lower parts are zero), as are small
+integers."""
 import numpy as np
 import pytest
 
@@ -12,7 +13,7 @@ from gpu_util import run_gpu, tol_mode
 
 pytestmark = pytest.mark.gpu
 
-MODES = {"fp16x3": mpow.MPOW_FP16X3, "bf16x3": mpow.MPOW_BF16X3}
+MODES = {"fp16x3": mpow.MPOW_FP16X3, "bf16x3": mpow.MPOW_BF16X3, "bf16x6": mpow.MPOW_BF16X6}
 
 
 @pytest.fixture(scope="module", params=list(MODES))
