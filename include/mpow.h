@@ -71,6 +71,21 @@ typedef enum mpow_mode {
     MPOW_BF16X6 = 3
 } mpow_mode;
 
+/* Tolerance-driven mode choice (host only).  Every mode states an accuracy
+ * bar: a result's relative Frobenius error against the exact power is at
+ * most max(ABS, FACTOR * floor), where floor is the problem's own relative
+ * sensitivity to float32-sized input noise (the change of A^p when every
+ * entry of A moves by a relative +-2^-24; 0 for a well-conditioned power):
+ *   MPOW_FP32, MPOW_FP16X3, MPOW_BF16X6   ABS 1e-5, FACTOR 64
+ *   MPOW_BF16X3                           ABS 2e-4, FACTOR 1024
+ * Returns the fastest mode whose bar is at most tol, in the order measured on
+ * MI355X (n = 4096): BF16X3 (2.4x the FP32 rate), FP16X3 (2.3x), BF16X6
+ * (1.35x), FP32.  wide_range != 0 skips FP16X3, whose parts lose entries
+ * below about 2^-38 of the matrix's norm (FP16's range after scaling); the
+ * BF16 modes keep float32's exponent range.  Returns -1 if no bar is met
+ * (tol below 1e-5, or tol or floor negative or NaN). */
+int mpow_mode_for_tolerance(double tol, double floor, int wide_range);
+
 /* Plan flags. */
 #define MPOW_FLAG_TIMING 1u /* record a pair of HIP events around every product
                                kernel launch; read with mpow_plan_timing */

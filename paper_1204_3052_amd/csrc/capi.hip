@@ -220,6 +220,16 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
     return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
 }
 
+int mpow_mode_for_tolerance(double tol, double floor, int wide_range) {
+    if (!(tol >= 0.0) || !(floor >= 0.0)) return -1;  // also rejects NaN
+    // stated bars: max(ABS, FACTOR * floor)
+    const double fp32_class = floor * 64.0 > 1e-5 ? floor * 64.0 : 1e-5;
+    const double bf16x3 = floor * 1024.0 > 2e-4 ? floor * 1024.0 : 2e-4;
+    if (bf16x3 <= tol) return MPOW_BF16X3;
+    if (fp32_class <= tol) return wide_range ? MPOW_BF16X6 : MPOW_FP16X3;
+    return -1;
+}
+
 mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel) {
     if (!plan) return MPOW_ERR_INVALID;
     bool ok = kernel == -1;

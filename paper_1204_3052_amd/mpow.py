@@ -56,7 +56,7 @@ EXPORTS = (
     "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_workspace_bytes",
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
-    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel",
+    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_mode_for_tolerance",
     "mpow_srv_create", "mpow_srv_submit", "mpow_srv_poll", "mpow_srv_wait_idle", "mpow_srv_stats",
     "mpow_srv_destroy", "mpow_srv_simulate",
 )
@@ -132,6 +132,7 @@ def _load():
         "mpow_plan_tile_table": (c.c_int, [P, P, c.c_int, c.c_int]),
         "mpow_plan_autotune": (c.c_int, [P, c.c_char_p, c.c_uint32]),
         "mpow_plan_set_kernel": (c.c_int, [P, c.c_int]),
+        "mpow_mode_for_tolerance": (c.c_int, [c.c_double, c.c_double, c.c_int]),
         "mpow_srv_create": (c.c_int, [c.POINTER(P), c.c_int, c.c_int, c.c_size_t, c.c_int, c.c_int, c.c_uint32]),
         "mpow_srv_submit": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_int, P, P, c.POINTER(c.c_uint64)]),
         "mpow_srv_poll": (c.c_int, [P, c.POINTER(Completion), c.c_int]),
@@ -229,6 +230,11 @@ def mpow_plan_timing(plan: int, kernel: int):
 
 def mpow_plan_timing_reset(plan: int) -> None:
     _check(_load().mpow_plan_timing_reset(plan), "mpow_plan_timing_reset")
+
+
+def mpow_mode_for_tolerance(tol: float, floor: float = 0.0, wide_range: bool = False) -> int:
+    """Fastest mode whose stated bar max(ABS, FACTOR * floor) is <= tol; -1 if none."""
+    return int(_load().mpow_mode_for_tolerance(float(tol), float(floor), 1 if wide_range else 0))
 
 
 def mpow_plan_set_kernel(plan: int, kernel: int) -> None:

@@ -105,3 +105,32 @@ def test_tolerance_modes_match_library():
     assert tolerance.tol_mode(mpow.MPOW_BF16X6, 0.0) == 1e-5
     assert tolerance.tol_fp32(0.0) == 1e-5 and tolerance.tol_fp32(1e-3) == 64e-3
     assert tolerance.tol_mode(mpow.MPOW_BF16X3, 0.0) == 2e-4
+
+
+def test_mode_for_tolerance(lib):
+    M = mpow
+    assert M.mpow_mode_for_tolerance(1e-3) == M.MPOW_BF16X3
+    assert M.mpow_mode_for_tolerance(2e-4) == M.MPOW_BF16X3
+    assert M.mpow_mode_for_tolerance(1e-4) == M.MPOW_FP16X3
+    assert M.mpow_mode_for_tolerance(1e-4, wide_range=True) == M.MPOW_BF16X6
+    assert M.mpow_mode_for_tolerance(1e-5) == M.MPOW_FP16X3
+    assert M.mpow_mode_for_tolerance(9e-6) == -1
+    assert M.mpow_mode_for_tolerance(float("nan")) == -1
+    assert M.mpow_mode_for_tolerance(1e-3, -1.0) == -1
+    # an ill-conditioned power: the floor term decides
+    assert M.mpow_mode_for_tolerance(5e-4, 1e-6) == M.MPOW_FP16X3
+    assert M.mpow_mode_for_tolerance(5e-5, 1e-6) == -1
+
+
+@pytest.mark.parametrize("floor", [0.0, 1e-9, 3e-7, 1e-6, 2e-5, 1e-3])
+@pytest.mark.parametrize("tol", [1e-6, 1e-5, 3e-5, 1e-4, 2e-4, 1e-3, 1e-2, 0.5])
+def test_mode_for_tolerance_meets_the_stated_bars(lib, tol, floor):
+    # the chosen mode's bar (oracle/tolerance.py, the bars the tests enforce)
+    # is within tol, and no faster mode's bar is
+    from oracle import tolerance
+    speed_order = [mpow.MPOW_BF16X3, mpow.MPOW_FP16X3, mpow.MPOW_BF16X6, mpow.MPOW_FP32]
+    for wide in (False, True):
+        m = mpow.mpow_mode_for_tolerance(tol, floor, wide)
+        ok = [x for x in speed_order if tolerance.tol_mode(x, floor) <= tol
+              and not (wide and x == mpow.MPOW_FP16X3)]
+        assert m == (ok[0] if ok else -1), (tol, floor, wide, m, ok)

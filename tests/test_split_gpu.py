@@ -160,3 +160,23 @@ def test_split_parity_large_ragged(mplan):
     A = inputs.gaussian(2100, 42)
     for p in (3, 17):
         check(mode, h, A, p, p)
+
+
+@pytest.mark.parametrize("n,p,tol,wide", [(512, 17, 3e-4, False), (512, 17, 3e-5, False),
+                                          (300, 100, 1e-3, True), (300, 100, 1e-4, True)])
+def test_mode_for_tolerance_end_to_end(n, p, tol, wide):
+    # the mode picked for a requested tolerance (with the oracle's floor of
+    # this input) meets that tolerance on the GPU
+    A = inputs.gaussian(n, 60 + n)
+    ref = oracle.mpow_binary(A, p)
+    floor = oracle.floor_estimate(A, p, inputs.relative_signs(n, 61 + n), ref=ref)
+    mode = mpow.mpow_mode_for_tolerance(tol, floor, wide)
+    assert mode >= 0
+    h = mpow.mpow_plan_create(0, n, 0, mode, 0)
+    try:
+        M, s = run_gpu(h, A, p)
+    finally:
+        mpow.mpow_plan_destroy(h)
+    err = oracle.rel_err(M, s, *ref)
+    print(f"    tol={tol} floor={floor:.2e} mode={mode} err={err:.3e}")
+    assert err <= tol
