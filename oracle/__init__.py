@@ -3,6 +3,7 @@
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  The GPU library never does, and the two share no code.
 """
+from .expm_oracle import expm, expm_squarings, taylor  # noqa: F401
 from .mpow_oracle import (  # noqa: F401
     exact_int_power,
     floor_estimate,
