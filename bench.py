@@ -482,6 +482,86 @@ PAPER_TIMES = {
 }
 
 
+def expm_workload(args):
+    """Matrix exponential e^A (scaling and squaring on the power's kernels):
+    N in {512, 2048, 4096}, N(0,1)/sqrt(N) entries scaled by 4 (||A||_F about
+    4 sqrt(N)).  Work = (7 Taylor products + j squarings) * 2N^3, with j
+    chosen from the norm (the timed calls pass it, so they do not wait for
+    the host).  The oracle leg checks N <= 2048 against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    from paper_1204_3052_amd import inputs, mpow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    plan = mpow.mpow_plan_create(0, 4096, 0, mpow.MPOW_FP32, mpow.MPOW_FLAG_EXPM)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    rows, kept = [], {}
+    for n in (512, 2048, 4096):
+        A_np = (inputs.gaussian(n, 11) * 4.0).astype(np.float32)
+        A = torch.from_numpy(A_np).to(dev)
+        out = torch.empty_like(A)
+        e = math.floor(math.log2(float(np.linalg.norm(A_np.astype(np.float64)))))
+        j = max(0, e + 2)
+        run = lambda: mpow.mpow_expm(plan, A.data_ptr(), n, out.data_ptr(), sc.data_ptr(), j, stream.cuda_stream)
+        for _ in range(max(args.warmup, 1)):
+            run()
+        torch.cuda.synchronize(dev)
+        times = []
+        for _ in range(max(args.steps, 1)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize(dev)
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        products = 7 + j
+        gflops = products * 2.0 * n ** 3 / ms / 1e6
+        rows.append({"n": n, "squarings": j, "products": products, "ms": round(ms, 3),
+                     "gflops": round(gflops, 1),
+                     "pct_fp32_mfma_peak": round(gflops / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2)})
+        if n <= 2048:
+            kept[n] = (A_np, out.cpu().numpy(), float(sc.item()))
+    mpow.mpow_plan_destroy(plan)
+    result = {"workload": "matrix exponential, N in {512,2048,4096}, 4 N(0,1)/sqrt(N) entries",
+              "unit": "GFLOP/s ((7 + j) 2N^3)", "results": rows}
+    if not args.no_cpu_baseline:
+        cpu, errs = expm_oracle_leg(kept)
+        result["cpu_baseline"] = cpu
+        for r in rows:
+            if r["n"] in errs:
+                r["rel_err"], r["tol"] = (float(f"{x:.3e}") for x in errs[r["n"]])
+                r["within_tol"] = errs[r["n"]][0] <= errs[r["n"]][1]
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def expm_oracle_leg(kept):
+    """The oracle beside the exponential: the FP64 oracle on each checked size
+    (timed: cpu_baseline), one perturbed run for the floor, errors and the
+    exponential's stated bar."""
+    import oracle
+    from oracle.tolerance import tol_expm
+    from paper_1204_3052_amd import inputs
+
+    spent, flop, errs = 0.0, 0.0, {}
+    for n, (A, M, s) in kept.items():
+        t = time.perf_counter()
+        ref = oracle.expm(A)
+        spent += time.perf_counter() - t
+        flop += (7 + oracle.expm_squarings(A)) * 2.0 * n ** 3
+        Rp = oracle.expm(oracle.perturbed(A, inputs.relative_signs(n, 4000 + n)))
+        floor = oracle.rel_err(Rp[0], Rp[1], *ref)
+        errs[n] = (oracle.rel_err(M, s, *ref), tol_expm(floor, oracle.expm_squarings(A)))
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": f"FP64 oracle matrix exponential at N in {sorted(kept)}; {spent:.1f} s "
+                     "(its own series runs to float64 resolution; rate counted as 7 + j products)"}
+    return cpu, errs
+
+
 def sequential_product_seconds(A_np) -> float:
     """The oracle beside the paper's table: one FP64 three-loop product on one
     host thread (the paper's sequential CPU method), timed."""
@@ -552,7 +632,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="plain", choices=["plain", "split", "batched", "serving", "paper"],
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "split", "batched", "serving", "paper", "expm"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
                          "at N=4096, p in {64, 1000}, with errors against the oracle")
     ap.add_argument("--duration", type=float, default=60.0,
@@ -586,6 +667,8 @@ def main():
         return serving_workload(args)
     if args.workload == "paper":
         return paper_workload(args)
+    if args.workload == "expm":
+        return expm_workload(args)
 
     import numpy as np
     import torch

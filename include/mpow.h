@@ -92,6 +92,8 @@ int mpow_mode_for_tolerance(double tol, double floor, int wide_range);
 #define MPOW_FLAG_POISON 2u /* testing: fill the workspace with NaN bytes at
                                creation instead of zeros, so a read of memory
                                the run has not written shows in the result */
+#define MPOW_FLAG_EXPM 4u   /* also allocate what mpow_expm needs: one more
+                               max_n x max_n float32 buffer (FP32 plans) */
 
 /* Upper bound on the number of products of one power (p < 2^63 needs <= 124). */
 #define MPOW_MAX_STEPS 126
@@ -158,6 +160,23 @@ mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *
  * DEVICE. */
 mpow_status mpow_run_naive(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
                            double *log2_scale, void *stream);
+
+/* Matrix exponential e^A by scaling and squaring, float32 products (the
+ * power's kernels; an extension beyond the paper, whose subject is A^p):
+ * e^A = (e^B)^(2^j) with B = A * 2^-j exact; e^B is the degree-8 Taylor
+ * polynomial by Horner's rule, I + B(I + B/2(... (I + B/8))), with
+ * ||B||_F < 1/2 (remainder below float32 resolution) when j is chosen from
+ * the norm; the j squarings are the power T^(2^j) of mpow_run.
+ *   A, n, out, log2_scale   as for mpow_run (out = M and *log2_scale = s
+ *              with e^A = M * 2^s, or out = e^A rounded to float32).
+ *   squarings  j in 0..62, or -1: j = max(0, floor(log2 ||A||_F) + 2),
+ *              0 for a zero or non-finite norm.  Choosing j reads the norm
+ *              back to the host: the call then waits for `stream` once.
+ * The plan must be a MPOW_FP32 plan created with MPOW_FLAG_EXPM.  Errors:
+ * INVALID (arguments, squarings outside -1..62), UNSUPPORTED (other plan,
+ * or -1 with ||A||_F >= 2^61), DEVICE. */
+mpow_status mpow_expm(mpow_plan_t plan, const float *A, int n, float *out, double *log2_scale,
+                      int squarings, void *stream);
 
 /* `count` independent powers in one call: matrix i is A[i] (device pointer,
  * n[i] x n[i]) raised to p[i] into out[i], with log2_scale[i] as in mpow_run

@@ -31,3 +31,13 @@ def tol_mode(mode: int, floor: float) -> float:
     if mode == MODE_BF16X3:
         return max(BF16X3_ABS_TOL, BF16X3_FLOOR_FACTOR * floor)
     return tol_fp32(floor)
+
+
+def tol_expm(floor: float, squarings: int) -> float:
+    """Bar of the float32 matrix exponential (scaling and squaring): the
+    float32 bar, or 4 * 2^j * 2^-24 when larger.  The Taylor polynomial of
+    B = A 2^-j carries a relative error of a few units of float32 rounding,
+    and each of the j squarings doubles a relative error, so the method's own
+    error grows as 2^j * 2^-24 whatever the input's sensitivity."""
+    return max(tol_fp32(floor), 4.0 * 2.0 ** squarings * 2.0 ** -24)
+

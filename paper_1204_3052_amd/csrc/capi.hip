@@ -86,7 +86,7 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     if (!out_plan) return MPOW_ERR_INVALID;
     *out_plan = nullptr;
     if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X6 ||
-        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON)) != 0)
+        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON | MPOW_FLAG_EXPM)) != 0)
         return MPOW_ERR_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -100,6 +100,9 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     const int wmax = workers[0] > workers[1] ? workers[0] : workers[1];
     const size_t ws_bytes = workspace_bytes(max_n, mode);
     const size_t b_bytes = max_batch > 0 ? batch_device_bytes(max_batch, batch_bmax(max_n), wmax) : 0;
+    // mpow_expm's Taylor polynomial and norm exponent
+    const bool expm = (flags & MPOW_FLAG_EXPM) && mode == MPOW_FP32;
+    const size_t e_bytes = expm ? round_up((size_t)max_n * max_n * sizeof(float), 256) + 256 : 0;
 
     mpow_plan *plan = new (std::nothrow) mpow_plan();
     if (!plan) return MPOW_ERR_NOMEM;
@@ -109,12 +112,24 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     plan->mode = mode;
     plan->flags = flags;
 
-    if (hipMalloc((void **)&plan->base, ws_bytes + b_bytes) != hipSuccess || !plan->base) {
+    if (hipMalloc((void **)&plan->base, ws_bytes + b_bytes + e_bytes) != hipSuccess || !plan->base) {
         (void)hipGetLastError();
         delete plan;
         return MPOW_ERR_NOMEM;
     }
-    if (hipMemset(plan->base, (flags & MPOW_FLAG_POISON) ? 0xFF : 0, ws_bytes + b_bytes) != hipSuccess) {
+    if (expm) {
+        plan->expm_T = (float *)(plan->base + ws_bytes + b_bytes);
+        plan->expm_e_dev = (int *)(plan->base + ws_bytes + b_bytes + e_bytes - 256);
+        if (hipHostMalloc((void **)&plan->expm_e_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(plan->base);
+            delete plan;
+            return MPOW_ERR_NOMEM;
+        }
+    }
+    if (hipMemset(plan->base, (flags & MPOW_FLAG_POISON) ? 0xFF : 0, ws_bytes + b_bytes + e_bytes) !=
+        hipSuccess) {
+        if (plan->expm_e_host) (void)hipHostFree(plan->expm_e_host);
         (void)hipFree(plan->base);
         delete plan;
         return MPOW_ERR_DEVICE;
@@ -125,6 +140,7 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
                            workers) != hipSuccess) {
         (void)hipGetLastError();
         batch_context_release(&plan->batch);
+        if (plan->expm_e_host) (void)hipHostFree(plan->expm_e_host);
         (void)hipFree(plan->base);
         delete plan;
         return MPOW_ERR_NOMEM;
@@ -139,6 +155,7 @@ mpow_status mpow_plan_destroy(mpow_plan_t plan) {
     (void)hipDeviceSynchronize();
     plan->timing.destroy();
     batch_context_release(&plan->batch);
+    if (plan->expm_e_host) (void)hipHostFree(plan->expm_e_host);
     (void)hipFree(plan->base);
     delete plan;
     return MPOW_SUCCESS;
@@ -187,6 +204,30 @@ mpow_status mpow_run_naive(mpow_plan_t plan, const float *A, int n, int64_t p, f
     TimingSink *t = (plan->flags & MPOW_FLAG_TIMING) ? &plan->timing : nullptr;
     const hipError_t e =
         enqueue_power_naive(plan->ws, A, n, p, out, log2_scale, (hipStream_t)stream, t);
+    return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
+}
+
+mpow_status mpow_expm(mpow_plan_t plan, const float *A, int n, float *out, double *log2_scale,
+                      int squarings, void *stream) {
+    const mpow_status st = check_run_args(plan, A, n, 1, out, log2_scale);
+    if (st != MPOW_SUCCESS) return st;
+    if (squarings < -1 || squarings > 62) return MPOW_ERR_INVALID;
+    if (plan->mode != MPOW_FP32 || !plan->expm_T) return MPOW_ERR_UNSUPPORTED;
+    DeviceGuard guard(plan->device);
+    if (!guard.ok) return device_error(plan, hipErrorInvalidDevice);
+    const hipStream_t s = (hipStream_t)stream;
+    int j = squarings;
+    if (j < 0) {
+        hipError_t e = enqueue_norm_exponent(plan->ws, A, n, plan->expm_e_dev, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(plan->expm_e_host, plan->expm_e_dev, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return device_error(plan, e);
+        j = expm_squarings_for(*plan->expm_e_host);
+        if (j > 62) return MPOW_ERR_UNSUPPORTED;
+    }
+    TimingSink *t = (plan->flags & MPOW_FLAG_TIMING) ? &plan->timing : nullptr;
+    const hipError_t e = enqueue_expm(plan->ws, plan->expm_T, A, n, j, out, log2_scale, s, t);
     return e == hipSuccess ? MPOW_SUCCESS : device_error(plan, e);
 }
 

@@ -10,7 +10,7 @@ namespace mpow {
 
 namespace {
 
-template <int BM, int BN, int WM, int WN, bool VEC, int KS>
+template <int BM, int BN, int WM, int WN, bool VEC, int KS, bool AXPI>
 __global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g) {
     constexpr int NT = WM * WN * KS * 64;
     __shared__ __attribute__((aligned(16))) float As[F32TileLds<BM, BN, KS>::A_FLOATS];
@@ -25,16 +25,20 @@ __global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g)
 
     // Scales of both operands from their partial sums of squares, reduced
     // while the first tile's loads are in flight.
+    // (an operand without partial sums takes the exponent given in the launch)
     auto scales = [&]() {
-        const int eX = exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red));
+        const int eX =
+            g.partX ? exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
         int eY = eX;
-        if (g.partY != g.partX)
+        if (!g.partY)
+            eY = g.eYfix;
+        else if (g.partY != g.partX)
             eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
         if (blockIdx.x == 0 && threadIdx.x == 0 && g.eSlot) *g.eSlot = eX;
         return OperandScales{pow2_neg(eX), pow2_neg(eY)};
     };
-    const double ss =
-        f32_tile<BM, BN, WM, WN, VEC, KS>(g.X, g.Y, scales, g.C, n, m0, n0, As, Bs, red);
+    const double ss = f32_tile<BM, BN, WM, WN, VEC, KS, AXPI>(g.X, g.Y, scales, g.C, n, m0, n0,
+                                                              As, Bs, red, VEC, g.alpha);
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
@@ -65,13 +69,20 @@ const Variant *variant(int id) {
 }
 
 template <int BM, int BN, int WM, int WN, int KS = 1>
-hipError_t launch_variant(const GemmLaunch &g, bool vec4, hipStream_t s) {
+hipError_t launch_variant(const GemmLaunch &g, bool vec4, bool axpi, hipStream_t s) {
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
     const dim3 block(WM * WN * KS * 64);
-    if (vec4)
-        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true, KS>), dim3(tiles), block, 0, s, g);
-    else
-        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false, KS>), dim3(tiles), block, 0, s, g);
+    if (axpi) {
+        if (vec4)
+            hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true, KS, true>), dim3(tiles), block, 0, s, g);
+        else
+            hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false, KS, true>), dim3(tiles), block, 0, s, g);
+    } else {
+        if (vec4)
+            hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true, KS, false>), dim3(tiles), block, 0, s, g);
+        else
+            hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false, KS, false>), dim3(tiles), block, 0, s, g);
+    }
     return hipGetLastError();
 }
 
@@ -104,22 +115,26 @@ const char *gemm_name(int kernel) {
     return v ? v->name : nullptr;
 }
 
-hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s) {
+hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s, bool axpi) {
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F32_128: return launch_variant<128, 128, 2, 2>(g, vec4, s);
-        case MPOW_KERNEL_GEMM_F32_64: return launch_variant<64, 64, 2, 2>(g, vec4, s);
-        case MPOW_KERNEL_GEMM_F32_32: return launch_variant<32, 32, 1, 1>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_128: return launch_variant<128, 128, 2, 2>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_64: return launch_variant<64, 64, 2, 2>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_32: return launch_variant<32, 32, 1, 1>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_256:
             // 16-byte loads only: the 4-byte-load form of this tile would spill
             if (!vec4) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1>),
-                               dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
+            if (axpi)
+                hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, true>),
+                                   dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
+            else
+                hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, false>),
+                                   dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
             return hipGetLastError();
-        case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, s);
-        case MPOW_KERNEL_GEMM_F32_32_K4: return launch_variant<32, 32, 1, 1, 4>(g, vec4, s);
-        case MPOW_KERNEL_GEMM_F32_32_K8: return launch_variant<32, 32, 1, 1, 8>(g, vec4, s);
-        case MPOW_KERNEL_GEMM_F32_64_K2: return launch_variant<64, 64, 2, 2, 2>(g, vec4, s);
-        case MPOW_KERNEL_GEMM_F32_128_K2: return launch_variant<128, 128, 2, 2, 2>(g, vec4, s);
+        case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_32_K4: return launch_variant<32, 32, 1, 1, 4>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_32_K8: return launch_variant<32, 32, 1, 1, 8>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_64_K2: return launch_variant<64, 64, 2, 2, 2>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_128_K2: return launch_variant<128, 128, 2, 2, 2>(g, vec4, axpi, s);
         default: return hipErrorInvalidValue;
     }
 }

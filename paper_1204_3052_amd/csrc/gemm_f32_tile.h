@@ -66,11 +66,14 @@ struct OperandScales {
 // 1 = 16-byte loads (n % 4 == 0, X and Y 16-byte aligned), 2 = chosen at run
 // time by `vec` with the register footprint of 1 (for kernels that handle
 // both cases and must not carry two copies of the tile loop).
-template <int BM, int BN, int WM, int WN, int VEC, int KS = 1, typename ScaleFn>
+//
+// AXPI selects the epilogue C = alpha * (X'Y') + I (one fused multiply-add
+// per element, the identity added on the diagonal) instead of C = X'Y'.
+template <int BM, int BN, int WM, int WN, int VEC, int KS = 1, bool AXPI = false, typename ScaleFn>
 __device__ __forceinline__ double f32_tile(const float *__restrict__ X, const float *__restrict__ Y,
                                            ScaleFn scales, float *__restrict__ C, int n, int m0,
                                            int n0, float *As, float *Bs, double *red,
-                                           bool vec = VEC == 1) {
+                                           bool vec = VEC == 1, float alpha = 1.0f) {
     typedef F32TileLds<BM, BN, KS> L;
     constexpr int NT = WM * WN * KS * 64;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -276,7 +279,8 @@ __device__ __forceinline__ double f32_tile(const float *__restrict__ X, const fl
                     const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
                     const int col = n0 + wn * TN + j * 32 + l32;
                     if (row < n && col < n) {
-                        const float v = acc[i][j][r];
+                        float v = acc[i][j][r];
+                        if constexpr (AXPI) v = fmaf(v, alpha, row == col ? 1.0f : 0.0f);
                         C[(int64_t)row * n + col] = v;
                         ss += (double)v * (double)v;
                     }

@@ -67,6 +67,14 @@ struct TimingSink {
 // Arguments must already be validated.  Returns the first HIP error.
 hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                          double *log2_scale, hipStream_t s, TimingSink *timing);
+// Matrix exponential: e^A = (Taylor-8 of 2^-j A)^(2^j) with T (n*n floats,
+// not part of ws) holding the Taylor polynomial; 0 <= j <= 62.
+hipError_t enqueue_expm(const Workspace &ws, float *T, const float *A, int n, int j, float *out,
+                        double *log2_scale, hipStream_t s, TimingSink *timing);
+// floor(log2 ||A||_F) into *dev_e (INT_MIN for a zero or non-finite norm).
+hipError_t enqueue_norm_exponent(const Workspace &ws, const float *A, int n, int *dev_e,
+                                 hipStream_t s);
+int expm_squarings_for(int e);  // max(0, e + 2); 0 for INT_MIN
 // The naive method: p - 1 chained float32 products X <- X.A (p <= MPOW_NAIVE_MAX_P).
 hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                                double *log2_scale, hipStream_t s, TimingSink *timing);
@@ -85,6 +93,9 @@ struct GemmLaunch {
     double *partC;           // output partials, one per tile
     int *eSlot;              // where block 0 records eX (may be null)
     int n;
+    // partX / partY null: the operand's exponent is eXfix / eYfix instead
+    int eXfix = 0, eYfix = 0;
+    float alpha = 1.0f;      // the identity-adding epilogue: C = alpha X'Y' + I
 };
 
 // Split of a float32 matrix into 16-bit hi/lo, row-major and transposed,
@@ -121,7 +132,8 @@ int gemm_pick(int n);                       // default kernel id for size n
 bool gemm_is_f32(int kernel);
 int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
 const char *gemm_name(int kernel);
-hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s);
+// axpi: the epilogue C = alpha X'Y' + I (matrix-exponential steps)
+hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s, bool axpi = false);
 
 // Scale and bookkeeping kernels.
 constexpr int kMaxNormBlocks = 1024;  // partial sums of A (capacity of Workspace::partA)
@@ -226,4 +238,7 @@ struct mpow_plan {
     mpow::Workspace ws;
     mpow::TimingSink timing;
     mpow::BatchContext batch;
+    float *expm_T = nullptr;    // Taylor polynomial of mpow_expm (MPOW_FLAG_EXPM)
+    int *expm_e_dev = nullptr;  // norm exponent of its input, device
+    int *expm_e_host = nullptr; // and its pinned host copy
 };

@@ -29,6 +29,7 @@ MPOW_BF16X6 = 3
 
 MPOW_FLAG_TIMING = 1
 MPOW_FLAG_POISON = 2
+MPOW_FLAG_EXPM = 4
 MPOW_TUNE_FORCE = 1
 TILE_TABLE_LEN = 17
 MPOW_MAX_STEPS = 126
@@ -54,7 +55,7 @@ MPOW_KERNEL_COUNT = 16
 # every symbol include/mpow.h declares
 EXPORTS = (
     "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_workspace_bytes",
-    "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched",
+    "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched", "mpow_expm",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
     "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_mode_for_tolerance",
     "mpow_srv_create", "mpow_srv_submit", "mpow_srv_poll", "mpow_srv_wait_idle", "mpow_srv_stats",
@@ -124,6 +125,7 @@ def _load():
         "mpow_plan_destroy": (c.c_int, [P]),
         "mpow_run": (c.c_int, [P, P, c.c_int, c.c_int64, P, P, P]),
         "mpow_run_naive": (c.c_int, [P, P, c.c_int, c.c_int64, P, P, P]),
+        "mpow_expm": (c.c_int, [P, P, c.c_int, P, P, c.c_int, P]),
         "mpow_run_batched": (c.c_int, [P, c.c_int, P, P, P, P, P, P]),
         "mpow_last_device_error": (c.c_int, [P]),
         "mpow_plan_timing": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_double),
@@ -200,6 +202,12 @@ def mpow_run_naive(plan: int, A: int, n: int, p: int, out: int, log2_scale: int 
                    stream: int | None) -> None:
     st = _load().mpow_run_naive(plan, A, int(n), int(p), out, log2_scale or None, stream or None)
     _check(st, "mpow_run_naive")
+
+
+def mpow_expm(plan: int, A: int, n: int, out: int, log2_scale: int | None, squarings: int,
+              stream: int | None) -> None:
+    st = _load().mpow_expm(plan, A, int(n), out, log2_scale or None, int(squarings), stream or None)
+    _check(st, "mpow_expm")
 
 
 def mpow_run_batched(plan: int, count: int, A_ptrs, ns, ps, out_ptrs, log2_scale: int | None,

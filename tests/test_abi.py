@@ -105,6 +105,7 @@ def test_tolerance_modes_match_library():
     assert tolerance.tol_mode(mpow.MPOW_BF16X6, 0.0) == 1e-5
     assert tolerance.tol_fp32(0.0) == 1e-5 and tolerance.tol_fp32(1e-3) == 64e-3
     assert tolerance.tol_mode(mpow.MPOW_BF16X3, 0.0) == 2e-4
+    assert tolerance.tol_expm(0.0, 0) == 1e-5 and tolerance.tol_expm(0.0, 10) == 4 * 2.0 ** -14
 
 
 def test_mode_for_tolerance(lib):
@@ -134,3 +135,7 @@ def test_mode_for_tolerance_meets_the_stated_bars(lib, tol, floor):
         ok = [x for x in speed_order if tolerance.tol_mode(x, floor) <= tol
               and not (wide and x == mpow.MPOW_FP16X3)]
         assert m == (ok[0] if ok else -1), (tol, floor, wide, m, ok)
+
+
+def test_expm_rejects_without_device(lib):
+    assert lib.mpow_expm(None, 16, 4, 32, None, -1, None) == mpow.MPOW_ERR_INVALID
