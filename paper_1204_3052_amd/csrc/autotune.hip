@@ -15,6 +15,7 @@ namespace {
 
 constexpr int kBuckets = kTileBuckets;
 constexpr int kShapes = kBatchShapes;  // tile shape ids of the batched kernel
+constexpr int kTunedShapes = 2;        // the shapes the autotuner times (0, 1)
 
 struct DevGuard {
     int prev = -1;
@@ -113,8 +114,8 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         return MPOW_ERR_DEVICE;
     }
 
-    const int wmax = plan->batch.workers[0] > plan->batch.workers[1] ? plan->batch.workers[0]
-                                                                    : plan->batch.workers[1];
+    int wmax = 0;
+    for (int w : plan->batch.workers) wmax = w > wmax ? w : wmax;
     const int count = plan->max_batch < 2 * wmax ? plan->max_batch : 2 * wmax;
     const size_t mat = (size_t)bmax * bmax;
     float *in = nullptr, *out = nullptr;
@@ -154,7 +155,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         const int n = b * 16;
         float best = 1e30f;
         int best_shape = plan->batch.cfg[b];
-        for (int shape = 0; shape < kShapes && st == MPOW_SUCCESS; ++shape) {
+        for (int shape = 0; shape < kTunedShapes && st == MPOW_SUCCESS; ++shape) {
             float t_min = 1e30f;
             for (int rep = 0; rep < 4 && st == MPOW_SUCCESS; ++rep) {
                 hdr->counter = 0;
@@ -170,7 +171,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                 float ms = 0.f;
                 if (hipMemcpyAsync(plan->batch.slot[0].desc, plan->batch.slot[0].host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
                     hipEventRecord(e0, s) != hipSuccess ||
-                    launch_batched(bl, plan->batch.workers[shape == 0], shape == 0, s) != hipSuccess ||
+                    launch_batched(bl, plan->batch.workers[shape == 0 ? 1 : 0], shape == 0 ? 1 : 0, s) != hipSuccess ||
                     hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                     st = MPOW_ERR_DEVICE;

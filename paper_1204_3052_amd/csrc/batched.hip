@@ -24,24 +24,23 @@ namespace mpow {
 
 namespace {
 
-constexpr int kNT = 256;
-
 // Whole-matrix loops of one workgroup keep kUnroll 16-byte loads in flight
 // per thread (a loop with one load per iteration waits out the memory
 // latency n^2 / 256 times).
 constexpr int kUnroll = 8;
 
+template <int NT>
 __device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, bool vec, double *red) {
     const int64_t total = (int64_t)n * n;
     double acc = 0.0;
     if (vec) {
         const f4 *M4 = (const f4 *)M;
         const int64_t t4 = total / 4;  // total is a multiple of 16 when n % 4 == 0
-        for (int64_t b = threadIdx.x; b < t4; b += kNT * kUnroll) {
+        for (int64_t b = threadIdx.x; b < t4; b += NT * kUnroll) {
             f4 v[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b + (int64_t)u * kNT;
+                const int64_t i = b + (int64_t)u * NT;
                 v[u] = i < t4 ? M4[i] : f4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
@@ -50,11 +49,11 @@ __device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, b
                 for (int c = 0; c < 4; ++c) acc += (double)v[u][c] * (double)v[u][c];
         }
     } else {
-        for (int64_t b = threadIdx.x; b < total; b += kNT * kUnroll) {
+        for (int64_t b = threadIdx.x; b < total; b += NT * kUnroll) {
             float v[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b + (int64_t)u * kNT;
+                const int64_t i = b + (int64_t)u * NT;
                 v[u] = i < total ? M[i] : 0.f;
             }
 #pragma unroll
@@ -64,7 +63,7 @@ __device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, b
     red[threadIdx.x] = acc;
     __syncthreads();
 #pragma unroll
-    for (int s = kNT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
@@ -74,6 +73,7 @@ __device__ __forceinline__ double wg_sumsq(const float *__restrict__ M, int n, b
 }
 
 // out = X * 2^-e (exact power-of-two scaling, split in two float factors).
+template <int NT>
 __device__ __forceinline__ void wg_scale_copy(const float *__restrict__ X, float *__restrict__ out,
                                               int n, bool vec, PowScale f) {
     const int64_t total = (int64_t)n * n;
@@ -81,30 +81,30 @@ __device__ __forceinline__ void wg_scale_copy(const float *__restrict__ X, float
         const f4 *X4 = (const f4 *)X;
         f4 *O4 = (f4 *)out;
         const int64_t t4 = total / 4;
-        for (int64_t b = threadIdx.x; b < t4; b += kNT * kUnroll) {
+        for (int64_t b = threadIdx.x; b < t4; b += NT * kUnroll) {
             f4 v[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b + (int64_t)u * kNT;
+                const int64_t i = b + (int64_t)u * NT;
                 if (i < t4) v[u] = X4[i];
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b + (int64_t)u * kNT;
+                const int64_t i = b + (int64_t)u * NT;
                 if (i < t4) O4[i] = v[u] * f.a * f.b;
             }
         }
     } else {
-        for (int64_t b = threadIdx.x; b < total; b += kNT * kUnroll) {
+        for (int64_t b = threadIdx.x; b < total; b += NT * kUnroll) {
             float v[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b + (int64_t)u * kNT;
+                const int64_t i = b + (int64_t)u * NT;
                 if (i < total) v[u] = X[i];
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int64_t i = b + (int64_t)u * kNT;
+                const int64_t i = b + (int64_t)u * NT;
                 if (i < total) out[i] = v[u] * f.a * f.b;
             }
         }
@@ -113,19 +113,20 @@ __device__ __forceinline__ void wg_scale_copy(const float *__restrict__ X, float
 
 // out = ldexp(X, s) in float64, rounded to float32 (overflow to inf,
 // underflow to zero).
+template <int NT>
 __device__ __forceinline__ void wg_ldexp_copy(const float *__restrict__ X, float *__restrict__ out,
                                               int n, int s) {
     const int64_t total = (int64_t)n * n;
-    for (int64_t b = threadIdx.x; b < total; b += kNT * kUnroll) {
+    for (int64_t b = threadIdx.x; b < total; b += NT * kUnroll) {
         float v[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = b + (int64_t)u * kNT;
+            const int64_t i = b + (int64_t)u * NT;
             if (i < total) v[u] = X[i];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = b + (int64_t)u * kNT;
+            const int64_t i = b + (int64_t)u * NT;
             if (i < total) out[i] = (float)ldexp((double)v[u], s);
         }
     }
@@ -134,7 +135,7 @@ __device__ __forceinline__ void wg_ldexp_copy(const float *__restrict__ X, float
 // One product C = (2^-eX X)(2^-eY Y) over all output tiles of an n x n
 // matrix; returns its sum of squares (tile sums added in tile order) to all
 // threads.
-template <int BM, int BN>
+template <int BM, int BN, int WM, int WN, int KS, int VEC = 2>
 __device__ __forceinline__ double wg_product(const float *X, int eX, const float *Y, int eY,
                                              float *C, int n, bool vec, float *As, float *Bs,
                                              double *red, double *bcast) {
@@ -150,7 +151,7 @@ __device__ __forceinline__ double wg_product(const float *X, int eX, const float
         // the whole matrix.
         asm volatile("" : "+s"(nn), "+s"(m0), "+s"(n0), "+s"(X), "+s"(Y), "+s"(C));
         const double ts =
-            f32_tile<BM, BN, 2, 2, 2>(X, Y, scales, C, nn, m0, n0, As, Bs, red, vec);
+            f32_tile<BM, BN, WM, WN, VEC, KS>(X, Y, scales, C, nn, m0, n0, As, Bs, red, vec);
         S += ts;  // meaningful in thread 0
     }
     if (threadIdx.x == 0) *bcast = S;
@@ -160,14 +161,32 @@ __device__ __forceinline__ double wg_product(const float *X, int eX, const float
     return S;
 }
 
-// Tile shape ids: 0 = 128x128, 1 = 64x64; both give bit-identical products.
-// BIG = false: the instance without the 128x128 tile (every cfg runs 64x64).
-template <bool BIG>
-__global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
-    constexpr int TB = BIG ? 128 : 64;  // largest tile edge of this instance
-    __shared__ __attribute__((aligned(16))) float As[F32TileLds<TB, TB>::A_FLOATS];
-    __shared__ __attribute__((aligned(16))) float Bs[F32TileLds<TB, TB>::B_FLOATS];
-    __shared__ double red[kNT];
+// Tile shape ids: 0 = 128x128, 1 = 64x64 (both give bit-identical
+// products), 2 = 256x256 with 8 waves.  Instances: INST 0 holds only 64x64
+// (every cfg runs 64x64), INST 1 holds 128x128 and 64x64, INST 2 (512
+// threads, one workgroup per CU) holds 256x256 and, for the other cfgs,
+// 128x128 on 8 waves.  All add each output's products in the same order.
+template <int INST>
+struct BatchInst {
+    static constexpr int NT = INST == 2 ? 512 : 256;
+    static constexpr int TB = INST == 0 ? 64 : (INST == 1 ? 128 : 256);
+    static constexpr int KS = INST == 2 ? 2 : 1;  // K split of the small tile in INST 2
+    static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+    static constexpr int A_FLOATS =
+        INST == 2 ? cmax(F32TileLds<256, 256>::A_FLOATS, F32TileLds<128, 128>::A_FLOATS)
+                  : F32TileLds<TB, TB>::A_FLOATS;
+    static constexpr int B_FLOATS =
+        INST == 2 ? cmax(F32TileLds<256, 256>::B_FLOATS, F32TileLds<128, 128>::B_FLOATS)
+                  : F32TileLds<TB, TB>::B_FLOATS;
+};
+
+template <int INST>
+__global__ __launch_bounds__(BatchInst<INST>::NT) void batched_kernel(BatchLaunch b) {
+    typedef BatchInst<INST> I;
+    constexpr int NT = I::NT;
+    __shared__ __attribute__((aligned(16))) float As[I::A_FLOATS];
+    __shared__ __attribute__((aligned(16))) float Bs[I::B_FLOATS];
+    __shared__ double red[NT];
     __shared__ double bcast;
     __shared__ int claimed;
 
@@ -190,7 +209,7 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
         const int64_t total = (int64_t)n * n;
 
         if (p == 0) {
-            for (int64_t i = threadIdx.x; i < total; i += kNT) {
+            for (int64_t i = threadIdx.x; i < total; i += NT) {
                 const int64_t r = i / n, c = i - r * n;
                 item.out[i] = (r == c) ? 1.0f : 0.0f;
             }
@@ -200,7 +219,7 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
         }
 
         const bool vec = (n % 4 == 0) && (((uintptr_t)item.A & 15) == 0);
-        const double SA = wg_sumsq(item.A, n, vec, red);
+        const double SA = wg_sumsq<NT>(item.A, n, vec, red);
         const int eA = exponent_of_sumsq(SA);
         const float *X = item.A;  // running matrix; its true value is X * 2^s
         int eX = eA;
@@ -216,10 +235,16 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
                     float *C = (k & 1) ? S1 : S0;
                     const float *Y = mul ? item.A : X;
                     const int eY = mul ? eA : eX;
-                    if (BIG && item.cfg == 0)
-                        SX = wg_product<TB, TB>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
-                    else
-                        SX = wg_product<64, 64>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+                    if (INST == 2) {
+                        if (item.cfg == 2)
+                            SX = wg_product<256, 256, 2, 4, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+                        else
+                            SX = wg_product<128, 128, 2, 4, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+                    } else if (INST == 1 && item.cfg == 0) {
+                        SX = wg_product<128, 128, 2, 2, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+                    } else {
+                        SX = wg_product<64, 64, 2, 2, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+                    }
                     s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
                     X = C;
                     eX = exponent_of_sumsq(SX);
@@ -231,12 +256,12 @@ __global__ __launch_bounds__(kNT) void batched_kernel(BatchLaunch b) {
         // finish: the same arithmetic as the single-matrix finish step
         if (item.scale) {
             const bool vec_out = (n % 4 == 0) && ((((uintptr_t)item.out | (uintptr_t)X) & 15) == 0);
-            wg_scale_copy(X, item.out, n, vec_out, pow2_neg(eX));
+            wg_scale_copy<NT>(X, item.out, n, vec_out, pow2_neg(eX));
             if (threadIdx.x == 0) *item.scale = (SX == 0.0) ? 0.0 : s + (double)eX;
         } else {
             double sc = s;
             sc = sc > 4000.0 ? 4000.0 : (sc < -4000.0 ? -4000.0 : sc);
-            wg_ldexp_copy(X, item.out, n, (int)sc);
+            wg_ldexp_copy<NT>(X, item.out, n, (int)sc);
         }
         __syncthreads();
     }
@@ -251,20 +276,26 @@ int batched_cfg_for(int n) {
     return p128 * p128 <= p64 * p64 ? 0 : 1;
 }
 
-int batched_occupancy(bool big) {
+int batched_occupancy(int inst) {
     int blocks = 0;
-    const hipError_t e =
-        big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<true>, kNT, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<false>, kNT, 0);
+    hipError_t e;
+    if (inst == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<2>, 512, 0);
+    else if (inst == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<1>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<0>, 256, 0);
     if (e != hipSuccess) return 1;
     return blocks < 1 ? 1 : blocks;
 }
 
-hipError_t launch_batched(const BatchLaunch &b, int grid, bool big, hipStream_t s) {
-    if (big)
-        hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(kNT), 0, s, b);
+hipError_t launch_batched(const BatchLaunch &b, int grid, int inst, hipStream_t s) {
+    if (inst == 2)
+        hipLaunchKernelGGL(batched_kernel<2>, dim3(grid), dim3(512), 0, s, b);
+    else if (inst == 1)
+        hipLaunchKernelGGL(batched_kernel<1>, dim3(grid), dim3(256), 0, s, b);
     else
-        hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(kNT), 0, s, b);
+        hipLaunchKernelGGL(batched_kernel<0>, dim3(grid), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

@@ -95,9 +95,10 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     }
     DeviceGuard guard(device);
     if (!guard.ok) return MPOW_ERR_DEVICE;
-    int workers[2] = {0, 0};
+    int workers[kBatchInstances] = {};
     if (max_batch > 0 && !batch_workers_for(device, workers)) return MPOW_ERR_DEVICE;
-    const int wmax = workers[0] > workers[1] ? workers[0] : workers[1];
+    int wmax = 0;
+    for (int w : workers) wmax = w > wmax ? w : wmax;
     const size_t ws_bytes = workspace_bytes(max_n, mode);
     const size_t b_bytes = max_batch > 0 ? batch_device_bytes(max_batch, batch_bmax(max_n), wmax) : 0;
     // mpow_expm's Taylor polynomial and norm exponent

@@ -168,12 +168,13 @@ struct BatchLaunch {
 };
 constexpr int kBatchMaxN = 256;
 constexpr int kTileBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
-constexpr int kBatchShapes = 2;
+constexpr int kBatchShapes = 3;   // tile shape ids of the batched kernel
+constexpr int kBatchInstances = 3;
 int batched_cfg_for(int n);
-// Resident workers per CU of the kernel instance with (big) or without the
-// 128x128 tile.
-int batched_occupancy(bool big);
-hipError_t launch_batched(const BatchLaunch &b, int grid, bool big, hipStream_t s);
+// Resident workers per CU of kernel instance inst (0: 64x64 only, 1: 128x128
+// and 64x64, 2: 256x256 and 128x128 with 8 waves).
+int batched_occupancy(int inst);
+hipError_t launch_batched(const BatchLaunch &b, int grid, int inst, hipStream_t s);
 
 // One descriptor buffer of a batch context: device descriptors, the pinned
 // host copy the descriptor copy reads, a captured graph (copy + launch) and
@@ -183,7 +184,7 @@ struct BatchSlot {
     void *host = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_count = -1;
-    bool graph_big = false;
+    int graph_inst = -1;
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -198,7 +199,7 @@ struct BatchContext {
     int last = -1; // slot of the previous batch
     float *scratch = nullptr;
     int64_t slot_floats = 0;
-    int workers[2] = {0, 0};  // [big]: grid of the instance without / with 128x128 tiles
+    int workers[kBatchInstances] = {};  // grid of each kernel instance
     int max_batch = 0;
     int cfg[kTileBuckets] = {};
     hipStream_t capture_stream = nullptr;
@@ -209,7 +210,7 @@ size_t batch_device_bytes(int max_batch, int bmax, int workers);
 // Sets up a context over [dev, dev + batch_device_bytes(..., max of
 // workers)); creates the pinned buffers, capture stream and events.
 hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax,
-                              const int workers[2]);
+                              const int workers[kBatchInstances]);
 void batch_context_release(BatchContext *bc);
 // Waits until every enqueued batch of the context has finished.
 hipError_t batch_wait_all(BatchContext *bc);
@@ -222,8 +223,8 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
                          hipStream_t s, bool use_graph, hipEvent_t *done = nullptr);
 
 // Resident workers of each batched kernel instance on `device` (CUs x
-// occupancy; [0] without, [1] with the 128x128 tile); false on failure.
-bool batch_workers_for(int device, int workers[2]);
+// occupancy); false on failure.
+bool batch_workers_for(int device, int workers[kBatchInstances]);
 
 }  // namespace mpow
 

@@ -300,24 +300,23 @@ size_t batch_device_bytes(int max_batch, int bmax, int workers) {
            round_up((size_t)workers * 2 * (size_t)batch_slot_floats(bmax) * sizeof(float), 256);
 }
 
-bool batch_workers_for(int device, int workers[2]) {
+bool batch_workers_for(int device, int workers[kBatchInstances]) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         cus < 1)
         return false;
-    for (int big = 0; big < 2; ++big) workers[big] = cus * batched_occupancy(big != 0);
+    for (int i = 0; i < kBatchInstances; ++i) workers[i] = cus * batched_occupancy(i);
     return true;
 }
 
 hipError_t batch_context_init(BatchContext *bc, char *dev, int max_batch, int bmax,
-                              const int workers[2]) {
+                              const int workers[kBatchInstances]) {
     const size_t desc = round_up(batch_desc_bytes(max_batch), 256);
     bc->slot[0].desc = dev;
     bc->slot[1].desc = dev + desc;
     bc->scratch = (float *)(dev + 2 * desc);
     bc->slot_floats = batch_slot_floats(bmax);
-    bc->workers[0] = workers[0];
-    bc->workers[1] = workers[1];
+    for (int i = 0; i < kBatchInstances; ++i) bc->workers[i] = workers[i];
     bc->max_batch = max_batch;
     for (int b = 0; b < kTileBuckets; ++b) bc->cfg[b] = batched_cfg_for(b * 16);
     for (int k = 0; k < 2; ++k) {
@@ -373,7 +372,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
     hdr->count = count;
     hdr->pad[0] = hdr->pad[1] = 0;
     BatchItem *items = (BatchItem *)(hdr + 1);
-    bool big = false;  // some matrix takes 128x128 tiles: the instance that has them
+    int inst = 0;  // the smallest kernel instance that holds every matrix's tile
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
         items[k].A = A[i];
@@ -382,9 +381,10 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         items[k].p = p[i];
         items[k].n = n[i];
         items[k].cfg = bc->cfg[(n[i] + 15) / 16];
-        big = big || items[k].cfg == 0;
+        const int need = items[k].cfg == 2 ? 2 : (items[k].cfg == 0 ? 1 : 0);
+        inst = need > inst ? need : inst;
     }
-    const int grid = bc->workers[big ? 1 : 0];
+    const int grid = bc->workers[inst];
     // Batches share the workers' scratch: order this one after the previous
     // one even when it was enqueued on another stream.
     if (bc->last >= 0 && bc->slot[bc->last].pending)
@@ -394,7 +394,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
     bl.scratch = bc->scratch;
     bl.slot_floats = bc->slot_floats;
     if (use_graph) {
-        if (!sl.graph_exec || sl.graph_count != count || sl.graph_big != big) {
+        if (!sl.graph_exec || sl.graph_count != count || sl.graph_inst != inst) {
             if (sl.graph_exec) {
                 (void)hipGraphExecDestroy(sl.graph_exec);
                 sl.graph_exec = nullptr;
@@ -403,7 +403,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
             MPOW_TRY(hipStreamBeginCapture(bc->capture_stream, hipStreamCaptureModeRelaxed));
             const hipError_t e1 = hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count),
                                                  hipMemcpyHostToDevice, bc->capture_stream);
-            const hipError_t e2 = launch_batched(bl, grid, big, bc->capture_stream);
+            const hipError_t e2 = launch_batched(bl, grid, inst, bc->capture_stream);
             const hipError_t e3 = hipStreamEndCapture(bc->capture_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -416,12 +416,12 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
                 return e4;
             }
             sl.graph_count = count;
-            sl.graph_big = big;
+            sl.graph_inst = inst;
         }
         MPOW_TRY(hipGraphLaunch(sl.graph_exec, s));
     } else {
         MPOW_TRY(hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count), hipMemcpyHostToDevice, s));
-        MPOW_TRY(launch_batched(bl, grid, big, s));
+        MPOW_TRY(launch_batched(bl, grid, inst, s));
     }
     MPOW_TRY(hipEventRecord(sl.done, s));
     sl.pending = true;

@@ -243,9 +243,10 @@ mpow_status mpow_srv_create(mpow_srv_t *out_srv, int device, int max_n, size_t h
     if (hipMalloc((void **)&srv->arena, hbm_budget) != hipSuccess) st = MPOW_ERR_NOMEM;
     if (st == MPOW_SUCCESS && max_batch > 0) {
         const int bmax = max_n < kBatchMaxN ? max_n : kBatchMaxN;
-        int workers[2] = {0, 0};
+        int workers[kBatchInstances] = {};
         const bool ok = batch_workers_for(device, workers);
-        const int wmax = workers[0] > workers[1] ? workers[0] : workers[1];
+        int wmax = 0;
+        for (int w : workers) wmax = w > wmax ? w : wmax;
         if (!ok ||
             hipMalloc((void **)&srv->batch_dev, batch_device_bytes(max_batch, bmax, wmax)) != hipSuccess ||
             batch_context_init(&srv->batch, srv->batch_dev, max_batch, bmax, workers) != hipSuccess)

@@ -223,10 +223,11 @@ def test_tile_shapes_bit_identical(plans):
     pk = Packed(mats)
     saved = mpow.mpow_plan_tile_table(hb)
     results = []
-    # all 128x128, all 64x64 (the instance without the large tile), and a
-    # mix of both shapes in one launch
+    # all 128x128, all 64x64 (the instance without the large tile), a mix of
+    # both in one launch, all 256x256 (the 8-wave instance), and a mix of all
     tables = [[0] * mpow.TILE_TABLE_LEN, [1] * mpow.TILE_TABLE_LEN,
-              [b % 2 for b in range(mpow.TILE_TABLE_LEN)]]
+              [b % 2 for b in range(mpow.TILE_TABLE_LEN)], [2] * mpow.TILE_TABLE_LEN,
+              [b % 3 for b in range(mpow.TILE_TABLE_LEN)]]
     for table in tables:
         mpow.mpow_plan_tile_table(hb, table)
         pk.out.fill_(float("nan"))
@@ -255,6 +256,6 @@ def test_autotune_and_cache(plans, tmp_path):
         assert mpow.mpow_plan_tile_table(h2)[1:] == table[1:]
     finally:
         mpow.mpow_plan_destroy(h2)
-    for bad in (2, 7, -1):
+    for bad in (3, 7, -1):
         with pytest.raises(mpow.MpowError):
             mpow.mpow_plan_tile_table(hb, [bad] * mpow.TILE_TABLE_LEN)
