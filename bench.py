@@ -161,7 +161,7 @@ def split_workload(args):
     return 0
 
 
-def split_oracle_leg(A_np, kept):
+def split_oracle_leg(A_np, kept, powers=(64, 1000)):
     """The oracle beside the split-precision runs: one FP64 oracle power per p
     (timed: cpu_baseline), one perturbed run per p for the floor, and every
     mode's error with its stated tolerance."""
@@ -171,7 +171,7 @@ def split_oracle_leg(A_np, kept):
 
     n = A_np.shape[0]
     flop, spent, errs = 0.0, 0.0, {}
-    for p in (64, 1000):
+    for p in powers:
         t = time.perf_counter()
         ref = oracle.mpow_binary(A_np, p)
         spent += time.perf_counter() - t
@@ -181,7 +181,7 @@ def split_oracle_leg(A_np, kept):
             if q == p:
                 errs[(name, p)] = (oracle.rel_err(M, s, *ref), tol_mode(mode, floor))
     cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
-           "sample": f"FP64 oracle binary exponentiation at N={n}, p in (64, 1000); {spent:.1f} s"}
+           "sample": f"FP64 oracle binary exponentiation at N={n}, p in {tuple(powers)}; {spent:.1f} s"}
     return cpu, errs
 
 
@@ -562,6 +562,68 @@ def expm_oracle_leg(kept):
     return cpu, errs
 
 
+def window_workload(args):
+    """Binary vs sliding-window schedules (MPOW_FLAG_WINDOW) on N in
+    {2048, 8192}, p in {1023, 2^20 - 1}: time per power and products.  The
+    rate is counted with each schedule's own product count."""
+    import numpy as np
+    import torch
+
+    from paper_1204_3052_amd import inputs, mpow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    plans = {"binary": mpow.mpow_plan_create(0, 8192, 0, mpow.MPOW_FP32, 0),
+             "window": mpow.mpow_plan_create(0, 8192, 0, mpow.MPOW_FP32, mpow.MPOW_FLAG_WINDOW)}
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    rows, kept = [], {}
+    for n in (2048, 8192):
+        A_np = inputs.gaussian(n, 1)
+        A = torch.from_numpy(A_np).to(dev)
+        out = torch.empty_like(A)
+        for p in (1023, 2 ** 20 - 1):
+            for name, h in plans.items():
+                G = mpow.mpow_gemm_count(p) if name == "binary" else len(mpow.mpow_window_schedule(p, 0)[0])
+                run = lambda: mpow.mpow_run(h, A.data_ptr(), n, p, out.data_ptr(), sc.data_ptr(), stream.cuda_stream)
+                for _ in range(max(args.warmup, 1)):
+                    run()
+                torch.cuda.synchronize(dev)
+                times = []
+                for _ in range(max(args.steps, 1)):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    run()
+                    e1.record(stream)
+                    torch.cuda.synchronize(dev)
+                    times.append(e0.elapsed_time(e1))
+                ms = float(np.median(times))
+                rows.append({"n": n, "p": p, "schedule": name, "products": G, "ms": round(ms, 3),
+                             "gflops": round(G * 2.0 * n ** 3 / ms / 1e6, 1)})
+                if n == 2048:
+                    kept[(name, p)] = (0, out.cpu().numpy(), float(sc.item()))
+    for h in plans.values():
+        mpow.mpow_plan_destroy(h)
+    result = {"workload": "binary vs sliding-window schedules, N(0,1)/sqrt(N) entries",
+              "unit": "GFLOP/s (the schedule's own products x 2N^3)", "results": rows}
+    if not args.no_cpu_baseline:
+        cpu, errs = window_oracle_leg(inputs.gaussian(2048, 1), kept)
+        result["cpu_baseline"] = cpu
+        for r in rows:
+            e = errs.get((r["schedule"], r["p"])) if r["n"] == 2048 else None
+            if e:
+                r["rel_err"], r["tol"] = float(f"{e[0]:.3e}"), float(f"{e[1]:.3e}")
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def window_oracle_leg(A_np, kept):
+    """The oracle beside the window schedules: one FP64 power per p at
+    N = 2048 (timed: cpu_baseline), one perturbed run for the floor, and both
+    schedules' errors with the float32 bar."""
+    return split_oracle_leg(A_np, kept, powers=(1023, 2 ** 20 - 1))
+
+
 def sequential_product_seconds(A_np) -> float:
     """The oracle beside the paper's table: one FP64 three-loop product on one
     host thread (the paper's sequential CPU method), timed."""
@@ -633,7 +695,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "split", "batched", "serving", "paper", "expm"],
+                    choices=["plain", "split", "batched", "serving", "paper", "expm", "window"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
                          "at N=4096, p in {64, 1000}, with errors against the oracle")
     ap.add_argument("--duration", type=float, default=60.0,
@@ -669,6 +731,8 @@ def main():
         return paper_workload(args)
     if args.workload == "expm":
         return expm_workload(args)
+    if args.workload == "window":
+        return window_workload(args)
 
     import numpy as np
     import torch

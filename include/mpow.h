@@ -94,6 +94,12 @@ int mpow_mode_for_tolerance(double tol, double floor, int wide_range);
                                the run has not written shows in the result */
 #define MPOW_FLAG_EXPM 4u   /* also allocate what mpow_expm needs: one more
                                max_n x max_n float32 buffer (FP32 plans) */
+#define MPOW_FLAG_WINDOW 8u /* FP32 plans: mpow_run follows the sliding-window
+                               schedule (mpow_window_schedule, w = 2 or 3) when
+                               it takes fewer products than binary; holds four
+                               more max_n x max_n buffers (A^2, A^3, A^5, A^7).
+                               Results then differ from the binary schedule's
+                               in rounding (same tolerance). */
 
 /* Upper bound on the number of products of one power (p < 2^63 needs <= 124). */
 #define MPOW_MAX_STEPS 126
@@ -116,6 +122,21 @@ int mpow_gemm_count(int64_t p);
  * cap < G(p).  Host only. */
 int mpow_schedule(int64_t p, uint8_t *ops, int cap);
 
+/* Sliding-window schedule of p >= 1 (host only; SURVEY-ranked extension:
+ * fewer products than binary exponentiation when p has long runs of ones,
+ * e.g. 27 instead of 38 for p = 2^20 - 1).  Windows of up to w bits, w in
+ * 1..3 (1 is the binary schedule of section 4.3), or w = 0 for the w with
+ * the fewest products.  The bits of p are read from the top; a zero bit
+ * squares the running matrix, a window (a run of at most w bits starting and
+ * ending with a one, value v) squares it once per bit and multiplies it by
+ * the precomputed odd power A^v; the first window starts from A^v.  Matrix
+ * slots: 0 = A, 1 = A^2, 2 = A^3, 3 = A^5, 4 = A^7, 5 and 6 = the running
+ * matrix.  Product k computes slot ops[3k] = slot ops[3k+1] . slot
+ * ops[3k+2]; *result receives the slot that holds A^p.  Returns the number
+ * of products (ops may be NULL to count only), or -1 (p < 1, w outside
+ * 0..3, result NULL, or cap too small). */
+int mpow_window_schedule(int64_t p, int w, uint8_t *ops, int cap, int *result);
+
 /* Device bytes a plan for (max_n, max_batch, mode) allocates; 0 for invalid
  * arguments.  Host only. */
 size_t mpow_workspace_bytes(int max_n, int max_batch, int mode);
@@ -125,7 +146,8 @@ size_t mpow_workspace_bytes(int max_n, int max_batch, int mode);
  * workspace is allocated here, never on the run path.  `mode` is an
  * mpow_mode.  On success *plan owns the workspace until mpow_plan_destroy.
  * Errors: INVALID (plan NULL, max_n < 1, max_batch < 0, unknown mode/flags),
- * UNSUPPORTED (mode not built), DEVICE (no such device / HIP failure),
+ * UNSUPPORTED (MPOW_FLAG_WINDOW with a mode other than MPOW_FP32), DEVICE (no
+ * such device / HIP failure),
  * NOMEM (allocation failed; nothing is leaked). */
 mpow_status mpow_plan_create(mpow_plan_t *plan, int device, int max_n, int max_batch,
                              int mode, uint32_t flags);

@@ -60,6 +60,23 @@ int mpow_gemm_count(int64_t p) {
     return top + __builtin_popcountll((unsigned long long)p) - 1;
 }
 
+int mpow_window_schedule(int64_t p, int w, uint8_t *ops, int cap, int *result) {
+    if (p < 1 || w < 0 || w > 3 || !result) return -1;
+    if (w == 0) {  // the fewest products over w = 1, 2, 3 (smaller w on ties)
+        int best = -1, bw = 1;
+        for (int v = 1; v <= 3; ++v) {
+            int r = 0;
+            const int g = window_schedule(p, v, nullptr, 0, &r);
+            if (g >= 0 && (best < 0 || g < best)) {
+                best = g;
+                bw = v;
+            }
+        }
+        w = bw;
+    }
+    return window_schedule(p, w, ops, cap, result);
+}
+
 int mpow_schedule(int64_t p, uint8_t *ops, int cap) {
     const int g = mpow_gemm_count(p);
     if (g < 0) return -1;
@@ -86,8 +103,9 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     if (!out_plan) return MPOW_ERR_INVALID;
     *out_plan = nullptr;
     if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X6 ||
-        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON | MPOW_FLAG_EXPM)) != 0)
+        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON | MPOW_FLAG_EXPM | MPOW_FLAG_WINDOW)) != 0)
         return MPOW_ERR_INVALID;
+    if ((flags & MPOW_FLAG_WINDOW) && mode != MPOW_FP32) return MPOW_ERR_UNSUPPORTED;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         (void)hipGetLastError();
@@ -104,6 +122,12 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     // mpow_expm's Taylor polynomial and norm exponent
     const bool expm = (flags & MPOW_FLAG_EXPM) && mode == MPOW_FP32;
     const size_t e_bytes = expm ? round_up((size_t)max_n * max_n * sizeof(float), 256) + 256 : 0;
+    // window schedules: A^2, A^3, A^5, A^7, their partial sums, the eY record
+    const bool window = (flags & MPOW_FLAG_WINDOW) != 0;
+    const size_t t32 = ((size_t)max_n + 31) / 32;
+    const size_t wbuf = round_up((size_t)max_n * max_n * sizeof(float), 256);
+    const size_t wpart = round_up(t32 * t32 * sizeof(double), 256);
+    const size_t w_bytes = window ? 4 * (wbuf + wpart) + round_up(kMaxGraphOps * sizeof(int), 256) : 0;
 
     mpow_plan *plan = new (std::nothrow) mpow_plan();
     if (!plan) return MPOW_ERR_NOMEM;
@@ -113,7 +137,8 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     plan->mode = mode;
     plan->flags = flags;
 
-    if (hipMalloc((void **)&plan->base, ws_bytes + b_bytes + e_bytes) != hipSuccess || !plan->base) {
+    if (hipMalloc((void **)&plan->base, ws_bytes + b_bytes + e_bytes + w_bytes) != hipSuccess ||
+        !plan->base) {
         (void)hipGetLastError();
         delete plan;
         return MPOW_ERR_NOMEM;
@@ -128,14 +153,22 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
             return MPOW_ERR_NOMEM;
         }
     }
-    if (hipMemset(plan->base, (flags & MPOW_FLAG_POISON) ? 0xFF : 0, ws_bytes + b_bytes + e_bytes) !=
-        hipSuccess) {
+    if (hipMemset(plan->base, (flags & MPOW_FLAG_POISON) ? 0xFF : 0,
+                  ws_bytes + b_bytes + e_bytes + w_bytes) != hipSuccess) {
         if (plan->expm_e_host) (void)hipHostFree(plan->expm_e_host);
         (void)hipFree(plan->base);
         delete plan;
         return MPOW_ERR_DEVICE;
     }
     workspace_carve(plan->base, max_n, mode, &plan->ws);
+    if (window) {
+        char *q = plan->base + ws_bytes + b_bytes + e_bytes;
+        for (int i = 0; i < 4; ++i) {
+            plan->ws.wp[i] = (float *)q; q += wbuf;
+            plan->ws.wpart[i] = (double *)q; q += wpart;
+        }
+        plan->ws.escaleY = (int *)q;
+    }
     if (max_batch > 0 &&
         batch_context_init(&plan->batch, plan->base + ws_bytes, max_batch, batch_bmax(max_n),
                            workers) != hipSuccess) {

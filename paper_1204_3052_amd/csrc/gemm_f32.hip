@@ -34,7 +34,10 @@ __global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g)
             eY = g.eYfix;
         else if (g.partY != g.partX)
             eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
-        if (blockIdx.x == 0 && threadIdx.x == 0 && g.eSlot) *g.eSlot = eX;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (g.eSlot) *g.eSlot = eX;
+            if (g.eSlotY) *g.eSlotY = eY;
+        }
         return OperandScales{pow2_neg(eX), pow2_neg(eY)};
     };
     const double ss = f32_tile<BM, BN, WM, WN, VEC, KS, AXPI>(g.X, g.Y, scales, g.C, n, m0, n0,

@@ -33,6 +33,11 @@ struct Workspace {
     int max_n = 0;
     int mode = MPOW_FP32;
     int kernel = -1;  // product kernel forced for every size, -1: per-size default
+    // window schedules (plans with MPOW_FLAG_WINDOW): A^2, A^3, A^5, A^7 with
+    // their partial sums, and the right operand's exponent of every product
+    float *wp[4] = {};
+    double *wpart[4] = {};
+    int *escaleY = nullptr;
 };
 
 size_t round_up(size_t x, size_t a);
@@ -62,6 +67,26 @@ struct TimingSink {
     void reset();
     void destroy();
 };
+
+// Sliding-window product schedules (float32 plans with MPOW_FLAG_WINDOW).
+// Matrix slots: A, A^2, A^3, A^5, A^7, and the running matrix's two buffers.
+constexpr int kSlotA = 0, kSlotA2 = 1, kSlotR0 = 5, kSlotR1 = 6, kSlots = 7;
+// Products of the window schedule of p with windows of up to w bits (1..3):
+// ops[3k], ops[3k+1], ops[3k+2] = destination, left and right slot of
+// product k (ops may be NULL to count); *result = the slot holding A^p.
+// Returns the number of products, -1 on bad arguments or cap too small.
+int window_schedule(int64_t p, int w, uint8_t *ops, int cap, int *result);
+
+// A window schedule as a kernel argument.
+constexpr int kMaxGraphOps = 128;
+struct GraphOps {
+    uint8_t op[kMaxGraphOps][3];  // dst, x, y slots of product k
+    int count;
+    int result;                   // the slot holding A^p
+};
+hipError_t launch_finish_graph(const float *C, int n, const double *partC, int nPartC,
+                               const int *eX, const int *eY, const GraphOps &g, float *out,
+                               double *log2_scale, hipStream_t s);
 
 // Enqueues A^p on stream s using workspace ws (ws.max_n >= n, ws.mode = mode).
 // Arguments must already be validated.  Returns the first HIP error.
@@ -93,6 +118,7 @@ struct GemmLaunch {
     double *partC;           // output partials, one per tile
     int *eSlot;              // where block 0 records eX (may be null)
     int n;
+    int *eSlotY = nullptr;   // where block 0 records eY (may be null)
     // partX / partY null: the operand's exponent is eXfix / eYfix instead
     int eXfix = 0, eYfix = 0;
     float alpha = 1.0f;      // the identity-adding epilogue: C = alpha X'Y' + I

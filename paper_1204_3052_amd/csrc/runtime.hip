@@ -116,6 +116,69 @@ void TimingSink::destroy() {
 
 // ---------------------------------------------------------------- one power
 
+// Left-to-right sliding-window schedule with windows of up to w bits (w = 1
+// is binary exponentiation).  The bits of p are read from the top; a zero
+// bit squares the running matrix R, and a window (a run of at most w bits
+// that starts and ends with a one, value v) squares R once per bit and then
+// multiplies it by the precomputed odd power A^v.  The first window sets R
+// to A^v itself.  The odd powers up to the largest v used are precomputed
+// as A^2 = A.A, A^3 = A.A^2, A^5 = A^3.A^2, ...  Slots: kSlotA, kSlotA2,
+// A^(2i+1) at kSlotA2 + i, and R alternating between kSlotR0 and kSlotR1.
+int window_schedule(int64_t p, int w, uint8_t *ops, int cap, int *result) {
+    if (p < 1 || w < 1 || w > 3) return -1;
+    const int top = 63 - __builtin_clzll((unsigned long long)p);
+    // windows, top down: len = bits covered, v = 0 for a lone zero bit
+    int wlen[64], wval[64], nw = 0, maxv = 1;
+    for (int i = top; i >= 0;) {
+        if (!((p >> i) & 1)) {
+            wlen[nw] = 1;
+            wval[nw++] = 0;
+            --i;
+            continue;
+        }
+        int j = i - w + 1 < 0 ? 0 : i - w + 1;
+        while (!((p >> j) & 1)) ++j;
+        const int v = (int)((p >> j) & ((1ll << (i - j + 1)) - 1));
+        wlen[nw] = i - j + 1;
+        wval[nw++] = v;
+        maxv = v > maxv ? v : maxv;
+        i = j - 1;
+    }
+    int k = 0;
+    auto emit = [&](int dst, int x, int y) -> bool {
+        if (ops) {
+            if (k >= cap) return false;
+            ops[3 * k] = (uint8_t)dst;
+            ops[3 * k + 1] = (uint8_t)x;
+            ops[3 * k + 2] = (uint8_t)y;
+        }
+        ++k;
+        return true;
+    };
+    auto slot_of = [](int v) { return v == 1 ? kSlotA : kSlotA2 + (v - 1) / 2; };
+    if (maxv >= 3) {
+        if (!emit(kSlotA2, kSlotA, kSlotA)) return -1;
+        for (int v = 3; v <= maxv; v += 2)
+            if (!emit(slot_of(v), slot_of(v - 2), kSlotA2)) return -1;
+    }
+    int R = slot_of(wval[0]);
+    auto next_r = [&]() { return R == kSlotR0 ? kSlotR1 : kSlotR0; };
+    for (int q = 1; q < nw; ++q) {
+        for (int s = 0; s < wlen[q]; ++s) {
+            const int d = next_r();
+            if (!emit(d, R, R)) return -1;
+            R = d;
+        }
+        if (wval[q]) {
+            const int d = next_r();
+            if (!emit(d, R, slot_of(wval[q]))) return -1;
+            R = d;
+        }
+    }
+    *result = R;
+    return k;
+}
+
 namespace {
 
 int schedule_of(int64_t p, uint8_t *ops) {
@@ -233,6 +296,49 @@ hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, cons
     return launch_finish(ws.buf[G & 1], n, ws.part[G & 1], tiles, ws.escale, p, out, log2_scale, s);
 }
 
+// Float32 products along a window schedule (ops from window_schedule, G >= 1).
+hipError_t run_fp32_window(const Workspace &ws, const float *A, int n, const uint8_t *ops,
+                           int G, int result, int nbA, float *out, double *log2_scale,
+                           hipStream_t s, TimingSink *timing) {
+    const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n);
+    if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
+    const int tiles = gemm_tiles(kernel, n);
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+    const float *mat[kSlots] = {A, ws.wp[0], ws.wp[1], ws.wp[2], ws.wp[3], ws.buf[0], ws.buf[1]};
+    double *part[kSlots] = {ws.partA, ws.wpart[0], ws.wpart[1], ws.wpart[2], ws.wpart[3],
+                            ws.part[0], ws.part[1]};
+    int npart[kSlots];
+    for (int i = 0; i < kSlots; ++i) npart[i] = i == kSlotA ? nbA : tiles;
+    GraphOps g{};
+    g.count = G;
+    g.result = result;
+    for (int k = 0; k < G; ++k) {
+        const int d = ops[3 * k], x = ops[3 * k + 1], y = ops[3 * k + 2];
+        g.op[k][0] = (uint8_t)d;
+        g.op[k][1] = (uint8_t)x;
+        g.op[k][2] = (uint8_t)y;
+        GemmLaunch L{};
+        L.X = mat[x];
+        L.partX = part[x];
+        L.nPartX = npart[x];
+        L.Y = mat[y];
+        L.partY = part[y];
+        L.nPartY = npart[y];
+        L.C = const_cast<float *>(mat[d]);
+        L.partC = part[d];
+        L.eSlot = ws.escale + k;
+        L.eSlotY = ws.escaleY + k;
+        L.n = n;
+        TimingRecord rec{};
+        if (timing) MPOW_TRY(timing->start(kernel, flop, s, &rec));
+        MPOW_TRY(gemm_launch(kernel, L, vec4, s));
+        if (timing) MPOW_TRY(timing->stop(&rec, s));
+    }
+    return launch_finish_graph(mat[result], n, part[result], npart[result], ws.escale, ws.escaleY,
+                               g, out, log2_scale, s);
+}
+
 }  // namespace
 
 hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
@@ -244,6 +350,23 @@ hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, 
     const int G = schedule_of(p, ops);
     if (G == 0) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     if (ws.mode != MPOW_FP32) return run_split(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
+    if (ws.escaleY) {
+        // a window schedule, when it takes fewer products than binary
+        uint8_t wops[3 * kMaxGraphOps];
+        int best = G, bw = 1, result = 0;
+        for (int w = 2; w <= 3; ++w) {
+            const int gw = window_schedule(p, w, nullptr, 0, &result);
+            if (gw >= 0 && gw < best) {
+                best = gw;
+                bw = w;
+            }
+        }
+        if (bw > 1) {
+            const int gw = window_schedule(p, bw, wops, kMaxGraphOps, &result);
+            if (gw > 0)
+                return run_fp32_window(ws, A, n, wops, gw, result, nbA, out, log2_scale, s, timing);
+        }
+    }
     return run_fp32(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
 }
 

@@ -83,6 +83,35 @@ __global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
                  (int64_t)blockIdx.x * kNT + threadIdx.x, (int64_t)gridDim.x * kNT);
 }
 
+// Final step of a window schedule: product k made slot dst = slot x . slot y
+// with operand exponents eX[k], eY[k]; a slot's log2 scale follows
+//   s(dst) = s(x) + eX + s(y) + eY,   s(A) = 0
+// (the binary recurrences are the special cases x = y and y = A).  C is the
+// result slot's matrix and partC its partial sums; otherwise as finish_kernel.
+__global__ __launch_bounds__(kNT) void finish_graph_kernel(const float *C, int n,
+                                                           const double *__restrict__ partC,
+                                                           int nPartC, const int *__restrict__ eX,
+                                                           const int *__restrict__ eY,
+                                                           GraphOps g, float *out,
+                                                           double *__restrict__ log2_scale) {
+    __shared__ double red[kNT];
+    __shared__ double sh_sG;
+    __shared__ int sh_eG;
+    const double S = block_sum_partials<kNT>(partC, nPartC, red);
+    if (threadIdx.x == 0) {
+        double s[kSlots];
+        for (int i = 0; i < kSlots; ++i) s[i] = 0.0;
+        for (int k = 0; k < g.count; ++k)
+            s[g.op[k][0]] = s[g.op[k][1]] + (double)eX[k] + s[g.op[k][2]] + (double)eY[k];
+        sh_sG = s[g.result];
+        sh_eG = exponent_of_sumsq(S);
+        if (log2_scale && blockIdx.x == 0) *log2_scale = (S == 0.0) ? 0.0 : sh_sG + (double)sh_eG;
+    }
+    __syncthreads();
+    finish_range(C, out, n, log2_scale != nullptr, sh_eG, sh_sG,
+                 (int64_t)blockIdx.x * kNT + threadIdx.x, (int64_t)gridDim.x * kNT);
+}
+
 int grid_for(int64_t total, int cap) {
     int64_t g = (total + kNT * 4 - 1) / (kNT * 4);
     if (g < 1) g = 1;
@@ -116,6 +145,14 @@ hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStre
 hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s) {
     hipLaunchKernelGGL(identity_kernel, dim3(grid_for((int64_t)n * n, 1024)), dim3(kNT), 0, s,
                        out, n, log2_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_graph(const float *C, int n, const double *partC, int nPartC,
+                              const int *eX, const int *eY, const GraphOps &g, float *out,
+                              double *log2_scale, hipStream_t s) {
+    hipLaunchKernelGGL(finish_graph_kernel, dim3(grid_for((int64_t)n * n, 2048)), dim3(kNT), 0, s,
+                       C, n, partC, nPartC, eX, eY, g, out, log2_scale);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ MPOW_BF16X6 = 3
 MPOW_FLAG_TIMING = 1
 MPOW_FLAG_POISON = 2
 MPOW_FLAG_EXPM = 4
+MPOW_FLAG_WINDOW = 8
 MPOW_TUNE_FORCE = 1
 TILE_TABLE_LEN = 17
 MPOW_MAX_STEPS = 126
@@ -54,7 +55,7 @@ MPOW_KERNEL_COUNT = 16
 
 # every symbol include/mpow.h declares
 EXPORTS = (
-    "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_workspace_bytes",
+    "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_window_schedule", "mpow_workspace_bytes",
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched", "mpow_expm",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
     "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_mode_for_tolerance",
@@ -120,6 +121,7 @@ def _load():
         "mpow_status_str": (c.c_char_p, [c.c_int]),
         "mpow_gemm_count": (c.c_int, [c.c_int64]),
         "mpow_schedule": (c.c_int, [c.c_int64, P, c.c_int]),
+        "mpow_window_schedule": (c.c_int, [c.c_int64, c.c_int, P, c.c_int, c.POINTER(c.c_int)]),
         "mpow_workspace_bytes": (c.c_size_t, [c.c_int, c.c_int, c.c_int]),
         "mpow_plan_create": (c.c_int, [c.POINTER(P), c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint32]),
         "mpow_plan_destroy": (c.c_int, [P]),
@@ -173,6 +175,18 @@ def mpow_schedule(p: int) -> list:
     if g < 0:
         raise MpowError(MPOW_ERR_INVALID, "mpow_schedule")
     return [int(ops[i]) for i in range(g)]
+
+
+def mpow_window_schedule(p: int, w: int = 0):
+    """(ops as a list of (dst, x, y) slot triples, result slot); w = 0: fewest products."""
+    c = ctypes
+    r = c.c_int(-1)
+    g = _load().mpow_window_schedule(int(p), int(w), None, 0, c.byref(r))
+    if g < 0:
+        raise MpowError(MPOW_ERR_INVALID, "mpow_window_schedule")
+    buf = (c.c_uint8 * max(3 * g, 1))()
+    g = _load().mpow_window_schedule(int(p), int(w), c.cast(buf, c.c_void_p), g, c.byref(r))
+    return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(g)], r.value
 
 
 def mpow_workspace_bytes(max_n: int, max_batch: int = 0, mode: int = MPOW_FP32) -> int:

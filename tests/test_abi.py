@@ -139,3 +139,39 @@ def test_mode_for_tolerance_meets_the_stated_bars(lib, tol, floor):
 
 def test_expm_rejects_without_device(lib):
     assert lib.mpow_expm(None, 16, 4, 32, None, -1, None) == mpow.MPOW_ERR_INVALID
+
+
+def replay_exponents(ops, result):
+    """Exponent of A held by every slot after the products (A = 1)."""
+    e = {0: 1}
+    for dst, x, y in ops:
+        assert x in e and y in e, (dst, x, y)  # operands written before use
+        e[dst] = e[x] + e[y]
+    return e[result]
+
+
+@pytest.mark.parametrize("p", list(range(1, 300)) + [1000, 1023, 4095, 12345, 2 ** 20 - 1, 2 ** 20,
+                                                      2 ** 62 + 5, 2 ** 63 - 1])
+def test_window_schedule_reaches_p(lib, p):
+    counts = {}
+    for w in (1, 2, 3):
+        ops, r = mpow.mpow_window_schedule(p, w)
+        assert replay_exponents(ops, r) == p, (p, w)
+        assert all(s < 7 for op in ops for s in op)
+        counts[w] = len(ops)
+    assert counts[1] == mpow.mpow_gemm_count(p)  # w = 1 is the binary schedule
+    ops, r = mpow.mpow_window_schedule(p, 0)
+    assert replay_exponents(ops, r) == p
+    assert len(ops) == min(counts.values())
+
+
+def test_window_schedule_counts_and_rejects(lib):
+    assert len(mpow.mpow_window_schedule(2 ** 20 - 1, 3)[0]) == 27
+    assert len(mpow.mpow_window_schedule(1023, 0)[0]) == 14
+    assert mpow.mpow_window_schedule(1, 0) == ([], 0)
+    r = ctypes.c_int()
+    assert lib.mpow_window_schedule(0, 0, None, 0, ctypes.byref(r)) == -1
+    assert lib.mpow_window_schedule(5, 4, None, 0, ctypes.byref(r)) == -1
+    assert lib.mpow_window_schedule(5, 1, None, 0, None) == -1
+    buf = (ctypes.c_uint8 * 3)()
+    assert lib.mpow_window_schedule(1023, 1, ctypes.cast(buf, ctypes.c_void_p), 1, ctypes.byref(r)) == -1
