@@ -22,7 +22,8 @@
  *    DEVICE pointers on the plan's device, owned by the caller; the library
  *    never frees or keeps them past the call's completion on the stream.
  *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).  Run
- *    calls only enqueue work; they never synchronise with the host.
+ *    calls only enqueue work; they never synchronise with the host (the one
+ *    exception: mpow_expm with squarings = -1 reads the input's norm back).
  *  - Every call returns an mpow_status; nothing throws across this boundary.
  *    Argument errors are detected on the host before anything is enqueued.
  *  - A plan is not thread-safe, and one plan must not have two runs in flight
@@ -42,7 +43,7 @@ extern "C" {
 typedef enum mpow_status {
     MPOW_SUCCESS = 0,
     MPOW_ERR_INVALID = 1,     /* bad argument (null, n<1, n>max_n, p<0, overlap) */
-    MPOW_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+    MPOW_ERR_UNSUPPORTED = 2, /* valid request the library does not implement */
     MPOW_ERR_NOMEM = 3,       /* device or pinned host allocation failed */
     MPOW_ERR_DEVICE = 4,      /* a HIP call failed; see mpow_last_device_error */
     MPOW_ERR_BUDGET = 5,      /* request can never fit the memory budget */
@@ -122,7 +123,7 @@ int mpow_gemm_count(int64_t p);
  * cap < G(p).  Host only. */
 int mpow_schedule(int64_t p, uint8_t *ops, int cap);
 
-/* Sliding-window schedule of p >= 1 (host only; SURVEY-ranked extension:
+/* Sliding-window schedule of p >= 1 (host only; an extension beyond the paper:
  * fewer products than binary exponentiation when p has long runs of ones,
  * e.g. 27 instead of 38 for p = 2^20 - 1).  Windows of up to w bits, w in
  * 1..3 (1 is the binary schedule of section 4.3), or w = 0 for the w with

@@ -1,6 +1,7 @@
 """FP64 CPU oracle for A^p (test infrastructure only).
 
-Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+Only tests, the smoke check and the benchmark's oracle legs (which time the
+oracle for the CPU baseline and check GPU results against it) may import
 this package.  The GPU library never does, and the two share no code.
 """
 from .expm_oracle import expm, expm_squarings, taylor  # noqa: F401

@@ -1,7 +1,8 @@
 """FP64 CPU oracle for the integer matrix power A^p.
 
-TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
-baseline leg of the benchmark may import this module.  It shares no code,
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's oracle legs (timing the oracle for the CPU baseline, checking GPU
+results against it) may import this module.  It shares no code,
 headers, tables or helpers with the GPU library, and the GPU library never
 imports it.
 

@@ -175,7 +175,7 @@ def test_graph_replays_with_eager_work_between(plans):
         assert np.array_equal(M, Mp) and s == sp
 
 
-def test_config3_ragged_4096(plans):
+def test_ragged_batch_4096(plans):
     # 4096 matrices, N uniform over multiples of 16 in [16, 256], p log-uniform
     # in [2, 1000], N(0,1)/sqrt(N) entries.
     hb, hp = plans

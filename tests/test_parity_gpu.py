@@ -112,30 +112,30 @@ def test_parity_nonlog_output(plan, n):
         assert err <= tol_fp32(floor), (n, p, err)
 
 
-def test_config1_row_stochastic(plan):
+def test_row_stochastic_n128_p64(plan):
     # Plain method, one 128x128 row-stochastic matrix, p = 64.
     n, p = 128, 64
     A = inputs.row_stochastic(n, 0)
     M, s = run_gpu(plan, A, p)
     err, tol, floor = check_against_oracle(M, s, A, p)
-    print(f"    config1 err={err:.3e} tol={tol:.3e}")
+    print(f"    row-stochastic err={err:.3e} tol={tol:.3e}")
     assert err <= 1e-5
     out, _ = run_gpu(plan, A, p, log_scale=False)
     assert float(np.max(np.abs(out.astype(np.float64).sum(axis=1) - 1.0))) <= 1e-5
 
 
 @pytest.mark.parametrize("n", [512, 2048])
-def test_config2_full_oracle(plan, n):
+def test_gaussian_full_oracle(plan, n):
     A = inputs.gaussian(n, 1)
     for p in (2, 17, 256, 1023):
         M, s = run_gpu(plan, A, p)
         err, tol, floor = check_against_oracle(M, s, A, p, seed=p)
-        print(f"    config2 n={n} p={p} err={err:.3e} tol={tol:.3e} floor={floor:.3e}")
+        print(f"    gaussian n={n} p={p} err={err:.3e} tol={tol:.3e} floor={floor:.3e}")
         assert err <= tol, (n, p, err, tol)
 
 
 @pytest.mark.parametrize("p", [2, 17])
-def test_config2_n8192_sampled_rows(plan, p):
+def test_gaussian_n8192_sampled_rows(plan, p):
     n = 8192
     A = inputs.gaussian(n, 1)
     M, s = run_gpu(plan, A, p)

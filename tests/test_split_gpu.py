@@ -52,7 +52,7 @@ def test_split_p0_p1(mplan):
     assert np.array_equal(out, A)
 
 
-def test_split_config4_n4096(mplan):
+def test_split_n4096_p64_p1000(mplan):
     # N = 4096, N(0,1)/sqrt(N) entries, p in {64, 1000}.
     mode, h = mplan
     A = inputs.gaussian(4096, 4)
