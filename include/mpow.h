@@ -138,8 +138,10 @@ int mpow_schedule(int64_t p, uint8_t *ops, int cap);
  * 0..3, result NULL, or cap too small). */
 int mpow_window_schedule(int64_t p, int w, uint8_t *ops, int cap, int *result);
 
-/* Device bytes a plan for (max_n, max_batch, mode) allocates; 0 for invalid
- * arguments.  Host only. */
+/* Device bytes a plan for (max_n, max_batch, mode) allocates without the
+ * optional buffers of MPOW_FLAG_EXPM (max_n^2 floats) and MPOW_FLAG_WINDOW
+ * (four max_n^2 float matrices and their per-tile partial sums); 0 for
+ * invalid arguments.  The batch part is sized for 256 CUs.  Host only. */
 size_t mpow_workspace_bytes(int max_n, int max_batch, int mode);
 
 /* Creates a plan on HIP device `device` for matrices up to max_n x max_n and
