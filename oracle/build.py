@@ -1,4 +1,4 @@
-"""Build the checker's C helper (test infrastructure; no GPU code)."""
+"""Build the oracle's C helper (test infrastructure; no GPU code)."""
 from __future__ import annotations
 
 import os

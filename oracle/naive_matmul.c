@@ -1,5 +1,5 @@
 /*
- * FP64 naive matrix product, test infrastructure only (the checker's side).
+ * FP64 naive matrix product, test infrastructure only (the oracle's side).
  *
  * This is the plain three-loop product of the paper's naive CPU method
  * (section 4.1): for every row i and column j, c[i][j] starts at zero and

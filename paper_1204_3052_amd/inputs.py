@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for matrix-power runs.
 
 This module only draws numbers.  It holds none of the power method's
-arithmetic, so both the FP64 checker and the GPU path can take their inputs
+arithmetic, so both the FP64 oracle and the GPU path can take their inputs
 from it.  Every generator uses NumPy's PCG64 (`numpy.random.default_rng`)
 with an explicit seed; matrices are drawn in float64 and handed out as
 contiguous row-major float32 arrays, which is the element type the library
