@@ -779,12 +779,18 @@ def main():
             kept[(n, p)] = (outs[n].cpu().numpy(), float(scales[i].item()))
 
     mpow.mpow_plan_timing_reset(plan)
+    # an event between consecutive steps (recorded on the stream, no host
+    # wait inside the timed region) gives per-step device times for p50/p99
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for i in range(args.steps):
         step()
+        marks[i + 1].record(stream)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
+    step_ms = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)])
 
     ms_step = dt / args.steps * 1e3
     value = flop_step * args.steps / dt / 1e9
@@ -807,6 +813,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "step_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                            "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
