@@ -46,7 +46,8 @@ def measured_traffic():
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        for key, name in (("kernel_source_sha256", "gemm_f32.hip"), ("tile_source_sha256", "gemm_f32_tile.h")):
+        for key, name in (("kernel_source_sha256", "gemm_f32.hip"), ("tile_source_sha256", "gemm_f32_tile.h"),
+                          ("dma_tile_source_sha256", "gemm_f32_dma.h")):
             sha = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
             if kv.get(key) != sha:
                 return None
@@ -763,16 +764,20 @@ def main():
 
     # per-case timing outside the timed region (context only); the results of
     # the sizes the oracle leg can reach are kept for its error check
+    # (median of a few back-to-back runs, so that the first case does not
+    # also carry the device waking up after the host's wait)
     per_case = []
     kept = {}
+    reps = 5
     for i, (n, p) in enumerate(cases):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        mpow.mpow_run(plan, mats[n].data_ptr(), n, p, outs[n].data_ptr(),
-                      scales[i:i + 1].data_ptr(), stream.cuda_stream)
-        e1.record(stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for r in range(reps):
+            mpow.mpow_run(plan, mats[n].data_ptr(), n, p, outs[n].data_ptr(),
+                          scales[i:i + 1].data_ptr(), stream.cuda_stream)
+            ev[r + 1].record(stream)
         torch.cuda.synchronize(dev)
-        ms = e0.elapsed_time(e1)
+        ms = float(np.median([ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]))
         per_case.append({"n": n, "p": p, "gemms": gemm_count(p), "ms": round(ms, 4),
                          "gflops": round(gemm_count(p) * 2.0 * n ** 3 / ms / 1e6, 1)})
         if n <= 2048:

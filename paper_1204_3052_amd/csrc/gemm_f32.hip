@@ -4,11 +4,32 @@
 // scales from the producers' partial sums of squares; the epilogue records
 // the tile's sum of squares for the next step.
 #include "mpow_internal.h"
+#include "gemm_f32_dma.h"
 #include "gemm_f32_tile.h"
 
 namespace mpow {
 
 namespace {
+
+// Both operand exponents of a product from their producers' partial sums of
+// squares (an operand without partial sums takes the exponent given in the
+// launch); block 0 records them for the log2-scale bookkeeping.  `red` is
+// LDS scratch of NT doubles; contains barriers.
+template <int NT>
+__device__ __forceinline__ OperandExps operand_exponents(const GemmLaunch &g, double *red) {
+    const int eX =
+        g.partX ? exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
+    int eY = eX;
+    if (!g.partY)
+        eY = g.eYfix;
+    else if (g.partY != g.partX)
+        eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (g.eSlot) *g.eSlot = eX;
+        if (g.eSlotY) *g.eSlotY = eY;
+    }
+    return OperandExps{eX, eY};
+}
 
 template <int BM, int BN, int WM, int WN, bool VEC, int KS, bool AXPI>
 __global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g) {
@@ -25,23 +46,31 @@ __global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g)
 
     // Scales of both operands from their partial sums of squares, reduced
     // while the first tile's loads are in flight.
-    // (an operand without partial sums takes the exponent given in the launch)
     auto scales = [&]() {
-        const int eX =
-            g.partX ? exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
-        int eY = eX;
-        if (!g.partY)
-            eY = g.eYfix;
-        else if (g.partY != g.partX)
-            eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            if (g.eSlot) *g.eSlot = eX;
-            if (g.eSlotY) *g.eSlotY = eY;
-        }
-        return OperandScales{pow2_neg(eX), pow2_neg(eY)};
+        const OperandExps e = operand_exponents<NT>(g, red);
+        return OperandScales{pow2_neg(e.x), pow2_neg(e.y)};
     };
     const double ss = f32_tile<BM, BN, WM, WN, VEC, KS, AXPI>(g.X, g.Y, scales, g.C, n, m0, n0,
                                                               As, Bs, red, VEC, g.alpha);
+    if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
+}
+
+// The 256 x 256 tile fed by LDS-DMA loads (gemm_f32_dma.h), for n % 4 == 0,
+// 16-byte aligned operands and n <= DMA_MAX_N.
+template <bool AXPI>
+__global__ __launch_bounds__(DMA_NT) void gemm_f32_dma_kernel(GemmLaunch g) {
+    __shared__ __attribute__((aligned(16))) float As0[DMA_ABUF];
+    __shared__ __attribute__((aligned(16))) float As1[DMA_ABUF];
+    __shared__ __attribute__((aligned(16))) float Bs0[DMA_BBUF];
+    __shared__ __attribute__((aligned(16))) float Bs1[DMA_BBUF];
+    __shared__ double red[DMA_NT];
+
+    const int n = g.n;
+    int tm, tn;
+    tile_of_block(blockIdx.x, (n + DMA_BM - 1) / DMA_BM, (n + DMA_BN - 1) / DMA_BN, &tm, &tn);
+    auto exps = [&]() { return operand_exponents<DMA_NT>(g, red); };
+    const double ss = f32_tile_dma<AXPI>(g.X, g.Y, exps, g.C, n, tm * DMA_BM, tn * DMA_BN, As0, As1,
+                                         Bs0, Bs1, red, g.alpha);
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
@@ -57,7 +86,7 @@ constexpr Variant kVariants[] = {
     {MPOW_KERNEL_GEMM_F32_128, 128, 128, 2, 2, 1, "gemm_f32_kernel<128,128,2,2>"},
     {MPOW_KERNEL_GEMM_F32_64, 64, 64, 2, 2, 1, "gemm_f32_kernel<64,64,2,2>"},
     {MPOW_KERNEL_GEMM_F32_32, 32, 32, 1, 1, 1, "gemm_f32_kernel<32,32,1,1>"},
-    {MPOW_KERNEL_GEMM_F32_256, 256, 256, 2, 4, 1, "gemm_f32_kernel<256,256,2,4>"},
+    {MPOW_KERNEL_GEMM_F32_256, 256, 256, 2, 4, 1, "gemm_f32_dma_kernel<256,256,2,4>"},
     {MPOW_KERNEL_GEMM_F32_128x64, 128, 64, 2, 2, 1, "gemm_f32_kernel<128,64,2,2>"},
     {MPOW_KERNEL_GEMM_F32_32_K4, 32, 32, 1, 1, 4, "gemm_f32_kernel<32,32,1,1,K4>"},
     {MPOW_KERNEL_GEMM_F32_32_K8, 32, 32, 1, 1, 8, "gemm_f32_kernel<32,32,1,1,K8>"},
@@ -126,12 +155,20 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
         case MPOW_KERNEL_GEMM_F32_256:
             // 16-byte loads only: the 4-byte-load form of this tile would spill
             if (!vec4) return hipErrorInvalidValue;
-            if (axpi)
+            if (g.n <= DMA_MAX_N) {
+                if (axpi)
+                    hipLaunchKernelGGL(gemm_f32_dma_kernel<true>, dim3(gemm_tiles(kernel, g.n)),
+                                       dim3(DMA_NT), 0, s, g);
+                else
+                    hipLaunchKernelGGL(gemm_f32_dma_kernel<false>, dim3(gemm_tiles(kernel, g.n)),
+                                       dim3(DMA_NT), 0, s, g);
+            } else if (axpi) {
                 hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, true>),
                                    dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
-            else
+            } else {
                 hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, false>),
                                    dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
+            }
             return hipGetLastError();
         case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_32_K4: return launch_variant<32, 32, 1, 1, 4>(g, vec4, axpi, s);

@@ -1,0 +1,254 @@
+// One 256 x 256 output tile of the float32 product C = (2^-eX X)(2^-eY Y)
+// whose operand tiles stream from memory straight into LDS (the paper's
+// tiled product, section 4.3.7, with the tiles kept consistent by barriers,
+// section 4.3.6).
+//
+// CDNA4 design (the large-n tile, where the MFMA pipes are the bound):
+//  - Buffer loads with the LDS-DMA form write each 16-byte chunk of the X
+//    (256 x 32) and Y (32 x 256) tiles into LDS without passing through
+//    VGPRs: no staging registers, no LDS store instructions, no per-element
+//    arithmetic on the way.  Lane l of a wave's load lands at byte 16 l of a
+//    1 KB LDS window, so the choice of which global chunk each lane fetches
+//    sets the LDS layout.  Out-of-range lanes get an offset beyond the
+//    buffer's range, which the hardware check turns into zeros (ragged
+//    edges).  The K advance of interior tiles is a scalar offset, so issuing
+//    a tile's loads costs no vector instructions.
+//  - Layouts are unpadded and XOR-swizzled so that the MFMA operand reads
+//    are free of LDS bank conflicts: in the X tile, 16-byte chunk c of row r
+//    sits at chunk position c ^ ((r >> 1) & 7); in the Y tile, rows 16..31
+//    swap their 32-float column halves.
+//  - Two LDS buffers (four separate arrays) alternate: the next K tile
+//    streams into one while the MFMAs read the other, one barrier per tile.
+//  - v_mfma_f32_32x32x2_f32 with the same wave tiling (2 x 4 waves, each a
+//    128 x 64 block of C) and the same k-to-lane mapping and K order as
+//    f32_tile, so each output element is accumulated in the same order.
+//  - The power-of-two operand scales: when eX + eY lies in [-32, 96] the
+//    unscaled product cannot leave the normal float range (|X Y| <=
+//    ||X||_F ||Y||_F < 2^(eX+eY+2)), so the factor 2^-(eX+eY) is applied
+//    once to each result in the epilogue; otherwise it is applied to the
+//    operand registers after each LDS read, as f32_tile applies it on load.
+//    Multiplying by a power of two is exact for normal floats and commutes
+//    with every rounding of the accumulation, so both forms give the bits of
+//    f32_tile wherever no product or partial sum is subnormal.
+#pragma once
+
+#include "gemm_f32_tile.h"
+#include "scale_device.h"
+
+namespace mpow {
+
+constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32;
+constexpr int DMA_WM = 2, DMA_WN = 4;
+constexpr int DMA_NT = DMA_WM * DMA_WN * 64;
+constexpr int DMA_ABUF = DMA_BM * DMA_BK;  // floats of one X tile buffer
+constexpr int DMA_BBUF = DMA_BK * DMA_BN;  // floats of one Y tile buffer
+// Largest n whose n x n float32 matrix a 32-bit buffer offset covers
+// (n^2 * 4 < 2^31).
+constexpr int DMA_MAX_N = 23170;
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Compile-time flag passed to the K loop's generic lambda.
+template <bool B>
+struct DmaBool {
+    static constexpr bool value = B;
+};
+
+// Operand exponents of one product.
+struct OperandExps {
+    int x, y;
+};
+
+// All 512 threads must call it.  `As0`/`As1` hold DMA_ABUF floats each,
+// `Bs0`/`Bs1` DMA_BBUF floats each (four distinct LDS arrays), `red`
+// DMA_WM * DMA_WN doubles.  `exps()` is called by every thread once, while
+// the first tile's loads are in flight; it may contain barriers.  Requires
+// n % 4 == 0, X and Y 16-byte aligned, n <= DMA_MAX_N.  Returns the tile's
+// float64 sum of squares of C in thread 0 (0 elsewhere).
+template <bool AXPI, typename ExpFn>
+__device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
+                                               const float *__restrict__ Y, ExpFn exps,
+                                               float *__restrict__ C, int n, int m0, int n0,
+                                               float *As0, float *As1, float *Bs0, float *Bs1,
+                                               double *red, float alpha = 1.0f) {
+    constexpr int NW = DMA_NT / 64;
+    constexpr int TM = DMA_BM / DMA_WM, TN = DMA_BN / DMA_WN;
+    constexpr int FM = TM / 32, FN = TN / 32;
+    constexpr int KH = DMA_BK / 2;
+    constexpr int A_PER = DMA_ABUF / 4 / (64 * NW);  // 1 KB loads per wave, X tile
+    constexpr int B_PER = DMA_BBUF / 4 / (64 * NW);  // 1 KB loads per wave, Y tile
+    static_assert(A_PER * 64 * NW * 4 == DMA_ABUF && B_PER * 64 * NW * 4 == DMA_BBUF, "loads");
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / DMA_WN, wn = wave % DMA_WN;
+    const int h = lane >> 5, l32 = lane & 31;
+    auto swz = [](int r) { return (r >> 1) & 7; };
+
+    const int bytes = n * n * 4;
+    const __amdgpu_buffer_rsrc_t rX =
+        __builtin_amdgcn_make_buffer_rsrc((void *)X, (short)0, bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rY =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Y, (short)0, bytes, 0x00020000);
+    constexpr unsigned OUT = 0x80000000u;  // beyond any buffer range: reads 0
+
+    // The lane's chunk of each 1 KB load.  X load r of this wave covers tile
+    // rows 8g .. 8g+7 (g = wave + r NW); Y load r covers tile row g.
+    int a_row[A_PER], a_col[A_PER], b_col[B_PER];
+    unsigned a_off[A_PER], b_off[B_PER];
+#pragma unroll
+    for (int r = 0; r < A_PER; ++r) {
+        const int row = 8 * (wave + r * NW) + (lane >> 3);
+        a_row[r] = m0 + row;
+        a_col[r] = 4 * ((lane & 7) ^ swz(row));
+        a_off[r] = a_row[r] < n ? (unsigned)((a_row[r] * n + a_col[r]) * 4) : OUT;
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER; ++r) {
+        const int g = wave + r * NW;
+        b_col[r] = n0 + 4 * (lane ^ (8 * ((g >> 4) & 1)));
+        b_off[r] = b_col[r] < n ? (unsigned)((g * n + b_col[r]) * 4) : OUT;
+    }
+    // K tile at k0 into (as, bs).  Interior tiles: fixed lane offsets plus
+    // a scalar K offset; the last, partial tile checks every chunk.
+    auto load_tile = [&](int k0, float *as, float *bs) {
+        if (k0 + DMA_BK <= n) {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r) {
+                const unsigned off = a_off[r], so = (unsigned)(k0 * 4);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rX, (lds_void_t *)(as + (wave + r * NW) * 256), 16, off, so, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < B_PER; ++r) {
+                const unsigned off = b_off[r], so = (unsigned)(k0 * n * 4);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rY, (lds_void_t *)(bs + (wave + r * NW) * 256), 16, off, so, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r) {
+                const int gc = k0 + a_col[r];
+                const unsigned off =
+                    (a_row[r] < n && gc < n) ? (unsigned)((a_row[r] * n + gc) * 4) : OUT;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rX, (lds_void_t *)(as + (wave + r * NW) * 256), 16, off, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < B_PER; ++r) {
+                const int gr = k0 + wave + r * NW;
+                const unsigned off =
+                    (gr < n && b_col[r] < n) ? (unsigned)((gr * n + b_col[r]) * 4) : OUT;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rY, (lds_void_t *)(bs + (wave + r * NW) * 256), 16, off, 0, 0, 0);
+            }
+        }
+    };
+
+    const int nk = (n + DMA_BK - 1) / DMA_BK;
+    load_tile(0, As0, Bs0);
+    const OperandExps e = exps();
+    const bool after = e.x + e.y >= -32 && e.x + e.y <= 96;  // scale in the epilogue
+    const PowScale fx = pow2_neg(e.x), fy = pow2_neg(e.y);
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's loads are in LDS
+    __syncthreads();
+
+    v16f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // K loop; SCALE_OPS scales the operand registers (the path for
+    // exponents outside the epilogue-safe range).
+    auto kloop = [&](auto scale_tag) {
+        constexpr bool SCALE_OPS = decltype(scale_tag)::value;
+        f4 a[2][FM];
+        float b[2][4][FN];
+        auto lds_read = [&](const float *as, const float *bs, int q, int st) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int row = wm * TM + i * 32 + l32;
+                a[st][i] = *(const f4 *)(as + row * DMA_BK + 4 * ((4 * h + q) ^ swz(row)));
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int k = h * KH + 4 * q + t;
+                    const int col = wn * TN + j * 32 + l32;
+                    b[st][t][j] = bs[k * DMA_BN + (col ^ (32 * h))];
+                }
+        };
+        auto body = [&](int kt, const float *as, const float *bs, float *an, float *bn) {
+            if (kt + 1 < nk) load_tile((kt + 1) * DMA_BK, an, bn);
+            lds_read(as, bs, 0, 0);
+#pragma unroll
+            for (int q = 0; q < KH / 4; ++q) {
+                const int st = q & 1;
+                if (q + 1 < KH / 4) lds_read(as, bs, q + 1, st ^ 1);
+                if constexpr (SCALE_OPS) {
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) a[st][i] = a[st][i] * fx.a * fx.b;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) b[st][t][j] = b[st][t][j] * fy.a * fy.b;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                                a[st][i][t], b[st][t][j], acc[i][j], 0, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): next tile is in LDS
+            __syncthreads();
+        };
+        for (int kt = 0; kt < nk; kt += 2) {
+            body(kt, As0, Bs0, As1, Bs1);
+            if (kt + 1 < nk) body(kt + 1, As1, Bs1, As0, Bs0);
+        }
+    };
+    if (after)
+        kloop(DmaBool<false>{});
+    else
+        kloop(DmaBool<true>{});
+
+    // 32x32 accumulator layout: register r of lane l holds row
+    // 8*(r/4) + 4*(l/32) + r%4 and column l%32 of the 32x32 block.
+    const PowScale fs = pow2_neg(after ? e.x + e.y : 0);
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int col = n0 + wn * TN + j * 32 + l32;
+                if (row < n && col < n) {
+                    float v = acc[i][j][r] * fs.a * fs.b;
+                    if constexpr (AXPI) v = fmaf(v, alpha, row == col ? 1.0f : 0.0f);
+                    C[(int64_t)row * n + col] = v;
+                    ss += (double)v * (double)v;
+                }
+            }
+    ss = wave_sum_lane0(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    double t = 0.0;
+    if (tid == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w];
+    }
+    __syncthreads();  // red and the LDS tiles may be reused by the caller
+    return t;
+}
+
+}  // namespace mpow

@@ -62,6 +62,23 @@ def test_expm_parity(eplan, n, scale):
     check(eplan, A, n)
 
 
+@pytest.mark.parametrize("n", [300, 1030])
+def test_expm_tile_shapes_bit_identical(eplan, n):
+    # The Taylor products' identity-adding epilogue on the 256 x 256 tile
+    # (scales applied to the sums) and on the 128 x 128 tile (scales applied
+    # on load) give the same bits; both meet the bar.
+    A = (inputs.gaussian(n, 170 + n) * 4.0).astype(np.float32)
+    runs = []
+    for k in (mpow.MPOW_KERNEL_GEMM_F32_256, mpow.MPOW_KERNEL_GEMM_F32_128):
+        mpow.mpow_plan_set_kernel(eplan, k)
+        try:
+            runs.append(check(eplan, A, n))
+        finally:
+            mpow.mpow_plan_set_kernel(eplan, -1)
+    (M0, s0), (M1, s1) = runs
+    assert s0 == s1 and np.array_equal(M0, M1)
+
+
 def test_expm_zero_is_identity(eplan):
     M, s = run_expm(eplan, np.zeros((9, 9), np.float32))
     assert np.array_equal(value(M, s), np.eye(9))

@@ -47,6 +47,25 @@ def test_same_order_kernels_bit_identical(fplan, n):
         assert err <= tol, (n, p, err, tol)
 
 
+@pytest.mark.parametrize("n", [300, 1030])
+def test_256_tile_operand_scale_paths(fplan, n):
+    # The 256 x 256 tile applies the operand scales 2^-eX, 2^-eY to its sums
+    # when eX + eY keeps the unscaled product in the normal range, else to the
+    # operands.  Inputs scaled by 2^k (exact) push the first product onto the
+    # second path: M must be bit-identical to the unscaled run's, s shifted by
+    # exactly k p, and both must equal the 128 x 128 tile's bits.
+    A = inputs.gaussian(n, 900 + n)
+    for p in (2, 17):
+        M0, s0 = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_256, A, p)
+        for k in (70, -40, -70):
+            Ak = np.ldexp(A, k).astype(np.float32)
+            assert np.array_equal(np.ldexp(Ak, -k), A)
+            M, s = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_256, Ak, p)
+            assert s == s0 + k * p and np.array_equal(M, M0), (n, p, k)
+            M1, s1 = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_128, Ak, p)
+            assert s1 == s and np.array_equal(M1, M), (n, p, k)
+
+
 @pytest.mark.parametrize("kernel", K_SPLIT)
 @pytest.mark.parametrize("n", SIZES)
 def test_k_split_kernels_parity_and_deterministic(fplan, kernel, n):
