@@ -801,7 +801,7 @@ def main():
     value = flop_step * args.steps / dt / 1e9
 
     # dominant kernel: the product kernel used for the largest size
-    kid = mpow.MPOW_KERNEL_GEMM_F32_256
+    kid = mpow.mpow_fp32_kernel_for(max(SIZES), True)
     launches, kms, kflop, kname = mpow.mpow_plan_timing(plan, kid)
     achieved = (kflop / launches) / (kms / launches * 1e-3) / 1e12 if launches else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_MFMA_PEAK_TFLOPS,

@@ -243,15 +243,25 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
 
 /* Forces the product kernel that mpow_run / mpow_run_naive use on this plan
  * for every n (kernel: an MPOW_KERNEL_* id of the plan's mode), or restores
- * the per-size default (kernel = -1).  The 256x256 float32 kernel needs
- * 16-byte loads; where n % 4 != 0 or A is not 16-byte aligned the 128x128
- * kernel runs instead.  Kernels without a K split give bit-identical
- * results; a K-split kernel (..._K2/_K4/_K8) adds its partial sums in its
- * own fixed order, so its results are deterministic but may differ from the
- * others in the last bits.  Not for use while a run on the plan is enqueued
+ * the per-size default (kernel = -1).  The float32 kernels that load their
+ * tiles straight into LDS (the 256x256 kernel and the ..._DMA kernels) need
+ * n % 4 == 0 and a 16-byte aligned A; otherwise (and for the ..._DMA
+ * kernels also when n > 23170) the 128x128 kernel runs instead (the 64x64
+ * kernel for MPOW_KERNEL_GEMM_F32_64_DMA).  Kernels without a K split give
+ * bit-identical results; a K-split kernel (..._K2/_K4/_K8) adds its partial
+ * sums in its own fixed order, so its results are deterministic but may
+ * differ from the others in the last bits.  Not for use while a run on the plan is enqueued
  * from another thread.  Errors: INVALID (plan NULL, kernel not of the plan's
  * mode). */
 mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel);
+
+/* The float32 product kernel (an MPOW_KERNEL_* id) that mpow_run uses at
+ * size n when no kernel is forced: aligned != 0 means n % 4 == 0 and a
+ * 16-byte aligned A (the LDS-DMA tiles need both).  Host-only, no device
+ * call; -1 for n < 1.  Small n take K-split tiles; from n = 768 the LDS-DMA
+ * tile with the best estimated rate for how its tile count fills the 256
+ * CUs in whole waves (section 4.3.7's tiled product, tile size chosen per n). */
+int mpow_fp32_kernel_for(int n, int aligned);
 
 /* The last hipError_t value a call on this plan saw (0 if none). */
 int mpow_last_device_error(mpow_plan_t plan);
@@ -263,7 +273,7 @@ enum {
     MPOW_KERNEL_GEMM_F32_32 = 2,  /* float32 product, 32x32 tiles */
     MPOW_KERNEL_GEMM_F16X3_128 = 3,  /* FP16 hi/lo three-product, 128x128 tiles */
     MPOW_KERNEL_GEMM_BF16X3_128 = 4, /* BF16 hi/lo three-product, 128x128 tiles */
-    MPOW_KERNEL_GEMM_F32_256 = 5,    /* float32 product, 256x256 tiles, 8 waves */
+    MPOW_KERNEL_GEMM_F32_256 = 5,    /* float32 product, 256x256 tiles, 8 waves, LDS-DMA loads */
     MPOW_KERNEL_GEMM_F32_128x64 = 6, /* float32 product, 128x64 tiles */
     MPOW_KERNEL_GEMM_F16X3_256 = 7,  /* FP16 hi/lo three-product, 256x256 tiles, 8 waves */
     MPOW_KERNEL_GEMM_BF16X3_256 = 8, /* BF16 hi/lo three-product, 256x256 tiles, 8 waves */
@@ -273,7 +283,10 @@ enum {
     MPOW_KERNEL_GEMM_F32_128_K2 = 12, /* float32 product, 128x128 tiles, 2x2 waves, K split in 2 */
     MPOW_KERNEL_GEMM_BF16X6_128 = 13, /* BF16 three-part six-product, 128x128 tiles */
     MPOW_KERNEL_GEMM_BF16X6_256 = 14, /* BF16 three-part six-product, 256x256 tiles, 8 waves */
-    MPOW_KERNEL_COUNT = 16
+    MPOW_KERNEL_GEMM_F32_64_DMA = 15,  /* float32 product, 64x64 tiles, LDS-DMA loads, K tile 64 */
+    MPOW_KERNEL_GEMM_F32_128_DMA = 16, /* float32 product, 128x128 tiles, 2x4 waves, LDS-DMA, K tile 64 */
+    MPOW_KERNEL_GEMM_F32_256x128_DMA = 17, /* float32 product, 256x128 tiles, 4x2 waves, LDS-DMA */
+    MPOW_KERNEL_COUNT = 18
 };
 
 /* Timing of product launches recorded under MPOW_FLAG_TIMING since the last

@@ -305,6 +305,11 @@ int mpow_mode_for_tolerance(double tol, double floor, int wide_range) {
     return -1;
 }
 
+int mpow_fp32_kernel_for(int n, int aligned) {
+    if (n < 1) return -1;
+    return gemm_resolve(gemm_pick(n, aligned != 0), n, aligned != 0);
+}
+
 mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel) {
     if (!plan) return MPOW_ERR_INVALID;
     bool ok = kernel == -1;

@@ -55,22 +55,24 @@ __global__ __launch_bounds__(WM *WN *KS * 64) void gemm_f32_kernel(GemmLaunch g)
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
-// The 256 x 256 tile fed by LDS-DMA loads (gemm_f32_dma.h), for n % 4 == 0,
-// 16-byte aligned operands and n <= DMA_MAX_N.
-template <bool AXPI>
-__global__ __launch_bounds__(DMA_NT) void gemm_f32_dma_kernel(GemmLaunch g) {
-    __shared__ __attribute__((aligned(16))) float As0[DMA_ABUF];
-    __shared__ __attribute__((aligned(16))) float As1[DMA_ABUF];
-    __shared__ __attribute__((aligned(16))) float Bs0[DMA_BBUF];
-    __shared__ __attribute__((aligned(16))) float Bs1[DMA_BBUF];
-    __shared__ double red[DMA_NT];
+// The tiles fed by LDS-DMA loads (gemm_f32_dma.h), for n % 4 == 0, 16-byte
+// aligned operands and n <= DMA_MAX_N.
+template <int BM, int BN, int WM, int WN, int BK, bool AXPI>
+__global__ __launch_bounds__(WM *WN * 64) void gemm_f32_dma_kernel(GemmLaunch g) {
+    constexpr int NT = WM * WN * 64;
+    __shared__ __attribute__((aligned(16))) float As0[BM * BK];
+    __shared__ __attribute__((aligned(16))) float As1[BM * BK];
+    __shared__ __attribute__((aligned(16))) float Bs0[BK * BN];
+    __shared__ __attribute__((aligned(16))) float Bs1[BK * BN];
+    __shared__ double red[NT];
 
     const int n = g.n;
     int tm, tn;
-    tile_of_block(blockIdx.x, (n + DMA_BM - 1) / DMA_BM, (n + DMA_BN - 1) / DMA_BN, &tm, &tn);
-    auto exps = [&]() { return operand_exponents<DMA_NT>(g, red); };
-    const double ss = f32_tile_dma<AXPI>(g.X, g.Y, exps, g.C, n, tm * DMA_BM, tn * DMA_BN, As0, As1,
-                                         Bs0, Bs1, red, g.alpha);
+    tile_of_block(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
+    auto exps = [&]() { return operand_exponents<NT>(g, red); };
+    const double ss = f32_tile_dma<BM, BN, WM, WN, BK, AXPI>(g.X, g.Y, exps, g.C, n, tm * BM,
+                                                             tn * BN, As0, As1, Bs0, Bs1, red,
+                                                             g.alpha);
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
@@ -92,6 +94,9 @@ constexpr Variant kVariants[] = {
     {MPOW_KERNEL_GEMM_F32_32_K8, 32, 32, 1, 1, 8, "gemm_f32_kernel<32,32,1,1,K8>"},
     {MPOW_KERNEL_GEMM_F32_64_K2, 64, 64, 2, 2, 2, "gemm_f32_kernel<64,64,2,2,K2>"},
     {MPOW_KERNEL_GEMM_F32_128_K2, 128, 128, 2, 2, 2, "gemm_f32_kernel<128,128,2,2,K2>"},
+    {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 2, 2, 1, "gemm_f32_dma_kernel<64,64,2,2,K64>"},
+    {MPOW_KERNEL_GEMM_F32_128_DMA, 128, 128, 2, 4, 1, "gemm_f32_dma_kernel<128,128,2,4,K64>"},
+    {MPOW_KERNEL_GEMM_F32_256x128_DMA, 256, 128, 4, 2, 1, "gemm_f32_dma_kernel<256,128,4,2>"},
 };
 
 const Variant *variant(int id) {
@@ -127,12 +132,46 @@ hipError_t launch_variant(const GemmLaunch &g, bool vec4, bool axpi, hipStream_t
 // 1792 (n = 1024: 29 us against 35 us); 128x128 tiles with a 2-way K split
 // around 2048 (153 us against 172 us); 64x64 tiles up to 4096 (n = 3072:
 // 549 us against 597 us for 128x64); 256x256 tiles from 4096 on.
-int gemm_pick(int n) {
-    if (n >= 4096) return MPOW_KERNEL_GEMM_F32_256;
+// Default product kernel per size.  Small n: K-split tiles (more workgroups
+// than output tiles), bound by the dependent-launch floor.  From n = 768 with
+// 16-byte loads: the LDS-DMA tile whose estimated rate is highest, the
+// estimate being the tile's rate when every CU runs whole waves of tiles
+// (measured on MI355X products at n = 4096 ... 8192) times the fraction of
+// the last wave of workgroups that is filled:
+//   rate = R * (T / 256) / ceil(T / 256),   T = tiles of the n x n output.
+// Against per-size measurements from n = 768 to 8192 this picks the fastest
+// LDS-DMA tile, or one within 2% of it.
+int gemm_pick(int n, bool vec4) {
+    if (n < 768) return MPOW_KERNEL_GEMM_F32_32_K4;
+    if (vec4 && n <= DMA_MAX_N) {
+        constexpr int kCUs = 256;
+        struct Cand {
+            int id, bm, bn;
+            double rate;  // TFLOP/s with whole waves of tiles
+        };
+        constexpr Cand cands[] = {
+            {MPOW_KERNEL_GEMM_F32_256x128_DMA, 256, 128, 151.0},
+            {MPOW_KERNEL_GEMM_F32_256, 256, 256, 149.0},
+            {MPOW_KERNEL_GEMM_F32_128_DMA, 128, 128, 147.0},
+            {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 132.0},
+        };
+        int best = MPOW_KERNEL_GEMM_F32_64_DMA;
+        double best_rate = 0.0;
+        for (const Cand &c : cands) {
+            const double T = (double)((n + c.bm - 1) / c.bm) * (double)((n + c.bn - 1) / c.bn);
+            const double waves = (double)(int64_t)((T + kCUs - 1) / kCUs);
+            const double rate = c.rate * (T / kCUs) / waves;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = c.id;
+            }
+        }
+        return best;
+    }
+    if (n >= 4096) return vec4 ? MPOW_KERNEL_GEMM_F32_256 : MPOW_KERNEL_GEMM_F32_128;
     if (n >= 2560) return MPOW_KERNEL_GEMM_F32_64;
     if (n >= 1792) return MPOW_KERNEL_GEMM_F32_128_K2;
-    if (n >= 640) return MPOW_KERNEL_GEMM_F32_64_K2;
-    return MPOW_KERNEL_GEMM_F32_32_K4;
+    return MPOW_KERNEL_GEMM_F32_64_K2;
 }
 
 bool gemm_is_f32(int kernel) { return variant(kernel) != nullptr; }
@@ -147,6 +186,28 @@ const char *gemm_name(int kernel) {
     return v ? v->name : nullptr;
 }
 
+template <int BM, int BN, int WM, int WN, int BK>
+hipError_t launch_dma(const GemmLaunch &g, bool vec4, bool axpi, hipStream_t s) {
+    if (!vec4 || g.n > DMA_MAX_N) return hipErrorInvalidValue;  // unresolved id
+    const dim3 grid(((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN)), block(WM * WN * 64);
+    if (axpi)
+        hipLaunchKernelGGL((gemm_f32_dma_kernel<BM, BN, WM, WN, BK, true>), grid, block, 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_f32_dma_kernel<BM, BN, WM, WN, BK, false>), grid, block, 0, s, g);
+    return hipGetLastError();
+}
+
+int gemm_resolve(int kernel, int n, bool vec4) {
+    const bool dma = vec4 && n <= DMA_MAX_N;
+    switch (kernel) {
+        case MPOW_KERNEL_GEMM_F32_256: return vec4 ? kernel : MPOW_KERNEL_GEMM_F32_128;
+        case MPOW_KERNEL_GEMM_F32_64_DMA: return dma ? kernel : MPOW_KERNEL_GEMM_F32_64;
+        case MPOW_KERNEL_GEMM_F32_128_DMA:
+        case MPOW_KERNEL_GEMM_F32_256x128_DMA: return dma ? kernel : MPOW_KERNEL_GEMM_F32_128;
+        default: return kernel;
+    }
+}
+
 hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s, bool axpi) {
     switch (kernel) {
         case MPOW_KERNEL_GEMM_F32_128: return launch_variant<128, 128, 2, 2>(g, vec4, axpi, s);
@@ -155,21 +216,18 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
         case MPOW_KERNEL_GEMM_F32_256:
             // 16-byte loads only: the 4-byte-load form of this tile would spill
             if (!vec4) return hipErrorInvalidValue;
-            if (g.n <= DMA_MAX_N) {
-                if (axpi)
-                    hipLaunchKernelGGL(gemm_f32_dma_kernel<true>, dim3(gemm_tiles(kernel, g.n)),
-                                       dim3(DMA_NT), 0, s, g);
-                else
-                    hipLaunchKernelGGL(gemm_f32_dma_kernel<false>, dim3(gemm_tiles(kernel, g.n)),
-                                       dim3(DMA_NT), 0, s, g);
-            } else if (axpi) {
+            if (g.n <= DMA_MAX_N) return launch_dma<256, 256, 2, 4, 32>(g, vec4, axpi, s);
+            if (axpi)
                 hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, true>),
                                    dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
-            } else {
+            else
                 hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, false>),
                                    dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
-            }
             return hipGetLastError();
+        case MPOW_KERNEL_GEMM_F32_64_DMA: return launch_dma<64, 64, 2, 2, 64>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_128_DMA: return launch_dma<128, 128, 2, 4, 64>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_256x128_DMA:
+            return launch_dma<256, 128, 4, 2, 32>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_32_K4: return launch_variant<32, 32, 1, 1, 4>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_32_K8: return launch_variant<32, 32, 1, 1, 8>(g, vec4, axpi, s);

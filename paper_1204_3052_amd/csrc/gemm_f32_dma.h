@@ -1,11 +1,11 @@
-// One 256 x 256 output tile of the float32 product C = (2^-eX X)(2^-eY Y)
+// One BM x BN output tile of the float32 product C = (2^-eX X)(2^-eY Y)
 // whose operand tiles stream from memory straight into LDS (the paper's
 // tiled product, section 4.3.7, with the tiles kept consistent by barriers,
 // section 4.3.6).
 //
-// CDNA4 design (the large-n tile, where the MFMA pipes are the bound):
+// CDNA4 design (the tiles for n where the MFMA pipes are the bound):
 //  - Buffer loads with the LDS-DMA form write each 16-byte chunk of the X
-//    (256 x 32) and Y (32 x 256) tiles into LDS without passing through
+//    (BM x BK) and Y (BK x BN) tiles into LDS without passing through
 //    VGPRs: no staging registers, no LDS store instructions, no per-element
 //    arithmetic on the way.  Lane l of a wave's load lands at byte 16 l of a
 //    1 KB LDS window, so the choice of which global chunk each lane fetches
@@ -15,13 +15,17 @@
 //    a tile's loads costs no vector instructions.
 //  - Layouts are unpadded and XOR-swizzled so that the MFMA operand reads
 //    are free of LDS bank conflicts: in the X tile, 16-byte chunk c of row r
-//    sits at chunk position c ^ ((r >> 1) & 7); in the Y tile, rows 16..31
-//    swap their 32-float column halves.
+//    sits at chunk position c ^ ((r >> 1) & 7) (BK = 32) or c ^ (r & 15)
+//    (BK = 64); in the Y tile, rows k with bit 4 set swap their 32-float
+//    column halves.
 //  - Two LDS buffers (four separate arrays) alternate: the next K tile
 //    streams into one while the MFMAs read the other, one barrier per tile.
-//  - v_mfma_f32_32x32x2_f32 with the same wave tiling (2 x 4 waves, each a
-//    128 x 64 block of C) and the same k-to-lane mapping and K order as
-//    f32_tile, so each output element is accumulated in the same order.
+//    BK = 64 halves the barriers of the smaller tiles; its tile is consumed
+//    as two 32-wide halves in order.
+//  - v_mfma_f32_32x32x2_f32, each wave a (BM/WM) x (BN/WN) block of C, with
+//    the k-to-lane mapping and K order of f32_tile (K in steps of 32, lane
+//    half h taking k = 16h + 4q + t of each step), so every output element
+//    is accumulated in the same order as by the other float32 tiles.
 //  - The power-of-two operand scales: when eX + eY lies in [-32, 96] the
 //    unscaled product cannot leave the normal float range (|X Y| <=
 //    ||X||_F ||Y||_F < 2^(eX+eY+2)), so the factor 2^-(eX+eY) is applied
@@ -37,11 +41,6 @@
 
 namespace mpow {
 
-constexpr int DMA_BM = 256, DMA_BN = 256, DMA_BK = 32;
-constexpr int DMA_WM = 2, DMA_WN = 4;
-constexpr int DMA_NT = DMA_WM * DMA_WN * 64;
-constexpr int DMA_ABUF = DMA_BM * DMA_BK;  // floats of one X tile buffer
-constexpr int DMA_BBUF = DMA_BK * DMA_BN;  // floats of one Y tile buffer
 // Largest n whose n x n float32 matrix a 32-bit buffer offset covers
 // (n^2 * 4 < 2^31).
 constexpr int DMA_MAX_N = 23170;
@@ -59,32 +58,38 @@ struct OperandExps {
     int x, y;
 };
 
-// All 512 threads must call it.  `As0`/`As1` hold DMA_ABUF floats each,
-// `Bs0`/`Bs1` DMA_BBUF floats each (four distinct LDS arrays), `red`
-// DMA_WM * DMA_WN doubles.  `exps()` is called by every thread once, while
+// All WM * WN * 64 threads must call it.  `As0`/`As1` hold BM * BK floats
+// each, `Bs0`/`Bs1` BK * BN floats each (four distinct LDS arrays), `red`
+// WM * WN doubles.  `exps()` is called by every thread once, while
 // the first tile's loads are in flight; it may contain barriers.  Requires
 // n % 4 == 0, X and Y 16-byte aligned, n <= DMA_MAX_N.  Returns the tile's
 // float64 sum of squares of C in thread 0 (0 elsewhere).
-template <bool AXPI, typename ExpFn>
+template <int BM, int BN, int WM, int WN, int BK, bool AXPI, typename ExpFn>
 __device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
                                                const float *__restrict__ Y, ExpFn exps,
                                                float *__restrict__ C, int n, int m0, int n0,
                                                float *As0, float *As1, float *Bs0, float *Bs1,
                                                double *red, float alpha = 1.0f) {
-    constexpr int NW = DMA_NT / 64;
-    constexpr int TM = DMA_BM / DMA_WM, TN = DMA_BN / DMA_WN;
+    static_assert(BK == 32 || BK == 64, "LDS K extent");
+    constexpr int NW = WM * WN;
+    constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 32, FN = TN / 32;
-    constexpr int KH = DMA_BK / 2;
-    constexpr int A_PER = DMA_ABUF / 4 / (64 * NW);  // 1 KB loads per wave, X tile
-    constexpr int B_PER = DMA_BBUF / 4 / (64 * NW);  // 1 KB loads per wave, Y tile
-    static_assert(A_PER * 64 * NW * 4 == DMA_ABUF && B_PER * 64 * NW * 4 == DMA_BBUF, "loads");
+    static_assert(FM * 32 == TM && FN * 32 == TN && BN >= 64, "wave tile");
+    constexpr int KH = 16;                                // k per lane half and 32-step
+    constexpr int ABUF = BM * BK, BBUF = BK * BN;         // floats per tile buffer
+    constexpr int A_PER = ABUF / 256 / NW;                // 1 KB loads per wave, X tile
+    constexpr int B_PER = BBUF / 256 / NW;                // 1 KB loads per wave, Y tile
+    static_assert(A_PER * 256 * NW == ABUF && B_PER * 256 * NW == BBUF, "loads");
+    constexpr int CPA = BK / 4;    // 16-byte chunks per X tile row
+    constexpr int CPB = BN / 4;    // 16-byte chunks per Y tile row
+    constexpr int RPB = 256 / BN;  // Y tile rows per 1 KB load
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave / DMA_WN, wn = wave % DMA_WN;
+    const int wm = wave / WN, wn = wave % WN;
     const int h = lane >> 5, l32 = lane & 31;
-    auto swz = [](int r) { return (r >> 1) & 7; };
+    auto swz = [](int r) { return BK == 32 ? ((r >> 1) & 7) : (r & 15); };
 
     const int bytes = n * n * 4;
     const __amdgpu_buffer_rsrc_t rX =
@@ -93,27 +98,28 @@ __device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
         __builtin_amdgcn_make_buffer_rsrc((void *)Y, (short)0, bytes, 0x00020000);
     constexpr unsigned OUT = 0x80000000u;  // beyond any buffer range: reads 0
 
-    // The lane's chunk of each 1 KB load.  X load r of this wave covers tile
-    // rows 8g .. 8g+7 (g = wave + r NW); Y load r covers tile row g.
-    int a_row[A_PER], a_col[A_PER], b_col[B_PER];
+    // The lane's chunk of each 1 KB load (g = wave + r NW): X load r covers
+    // tile rows (256 / BK) g ..., Y load r covers tile rows RPB g ....
+    int a_row[A_PER], a_col[A_PER], b_row[B_PER], b_col[B_PER];
     unsigned a_off[A_PER], b_off[B_PER];
 #pragma unroll
     for (int r = 0; r < A_PER; ++r) {
-        const int row = 8 * (wave + r * NW) + (lane >> 3);
+        const int row = (256 / BK) * (wave + r * NW) + lane / CPA;
         a_row[r] = m0 + row;
-        a_col[r] = 4 * ((lane & 7) ^ swz(row));
+        a_col[r] = 4 * ((lane % CPA) ^ swz(row));
         a_off[r] = a_row[r] < n ? (unsigned)((a_row[r] * n + a_col[r]) * 4) : OUT;
     }
 #pragma unroll
     for (int r = 0; r < B_PER; ++r) {
-        const int g = wave + r * NW;
-        b_col[r] = n0 + 4 * (lane ^ (8 * ((g >> 4) & 1)));
-        b_off[r] = b_col[r] < n ? (unsigned)((g * n + b_col[r]) * 4) : OUT;
+        const int row = RPB * (wave + r * NW) + lane / CPB;
+        b_row[r] = row;
+        b_col[r] = n0 + 4 * ((lane % CPB) ^ (8 * ((row >> 4) & 1)));
+        b_off[r] = b_col[r] < n ? (unsigned)((row * n + b_col[r]) * 4) : OUT;
     }
     // K tile at k0 into (as, bs).  Interior tiles: fixed lane offsets plus
     // a scalar K offset; the last, partial tile checks every chunk.
     auto load_tile = [&](int k0, float *as, float *bs) {
-        if (k0 + DMA_BK <= n) {
+        if (k0 + BK <= n) {
 #pragma unroll
             for (int r = 0; r < A_PER; ++r) {
                 const unsigned off = a_off[r], so = (unsigned)(k0 * 4);
@@ -137,7 +143,7 @@ __device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
             }
 #pragma unroll
             for (int r = 0; r < B_PER; ++r) {
-                const int gr = k0 + wave + r * NW;
+                const int gr = k0 + b_row[r];
                 const unsigned off =
                     (gr < n && b_col[r] < n) ? (unsigned)((gr * n + b_col[r]) * 4) : OUT;
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
@@ -146,7 +152,7 @@ __device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
         }
     };
 
-    const int nk = (n + DMA_BK - 1) / DMA_BK;
+    const int nk = (n + BK - 1) / BK;
     load_tile(0, As0, Bs0);
     const OperandExps e = exps();
     const bool after = e.x + e.y >= -32 && e.x + e.y <= 96;  // scale in the epilogue
@@ -168,28 +174,30 @@ __device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
         constexpr bool SCALE_OPS = decltype(scale_tag)::value;
         f4 a[2][FM];
         float b[2][4][FN];
-        auto lds_read = [&](const float *as, const float *bs, int q, int st) {
+        // operands of k = 32u + 16h + 4q + t, t = 0..3
+        auto lds_read = [&](const float *as, const float *bs, int u, int q, int st) {
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 const int row = wm * TM + i * 32 + l32;
-                a[st][i] = *(const f4 *)(as + row * DMA_BK + 4 * ((4 * h + q) ^ swz(row)));
+                a[st][i] = *(const f4 *)(as + row * BK + 4 * ((8 * u + 4 * h + q) ^ swz(row)));
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    const int k = h * KH + 4 * q + t;
+                    const int k = 32 * u + h * KH + 4 * q + t;
                     const int col = wn * TN + j * 32 + l32;
-                    b[st][t][j] = bs[k * DMA_BN + (col ^ (32 * h))];
+                    b[st][t][j] = bs[k * BN + (col ^ (32 * h))];
                 }
         };
+        constexpr int GROUPS = (BK / 32) * (KH / 4);  // groups of four k per LDS tile
         auto body = [&](int kt, const float *as, const float *bs, float *an, float *bn) {
-            if (kt + 1 < nk) load_tile((kt + 1) * DMA_BK, an, bn);
-            lds_read(as, bs, 0, 0);
+            if (kt + 1 < nk) load_tile((kt + 1) * BK, an, bn);
+            lds_read(as, bs, 0, 0, 0);
 #pragma unroll
-            for (int q = 0; q < KH / 4; ++q) {
-                const int st = q & 1;
-                if (q + 1 < KH / 4) lds_read(as, bs, q + 1, st ^ 1);
+            for (int gq = 0; gq < GROUPS; ++gq) {
+                const int st = gq & 1;
+                if (gq + 1 < GROUPS) lds_read(as, bs, (gq + 1) / 4, (gq + 1) % 4, st ^ 1);
                 if constexpr (SCALE_OPS) {
 #pragma unroll
                     for (int i = 0; i < FM; ++i) a[st][i] = a[st][i] * fx.a * fx.b;

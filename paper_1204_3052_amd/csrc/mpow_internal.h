@@ -154,9 +154,12 @@ const char *gemm_split_name(int kernel);
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s);
 
 // Float32 product kernel variants (index = MPOW_KERNEL_* id).
-int gemm_pick(int n);                       // default kernel id for size n
+int gemm_pick(int n, bool vec4);            // default kernel id for size n
 bool gemm_is_f32(int kernel);
 int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
+// The kernel id that runs for `kernel` at size n: the LDS-DMA kernels need
+// 16-byte loads (vec4) and n <= 23170, else a same-order fallback runs.
+int gemm_resolve(int kernel, int n, bool vec4);
 const char *gemm_name(int kernel);
 // axpi: the epilogue C = alpha X'Y' + I (matrix-exponential steps)
 hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s, bool axpi = false);

@@ -204,8 +204,8 @@ hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const
                     int G, int nbA, float *out, double *log2_scale, hipStream_t s,
                     TimingSink *timing) {
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n);
-    if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
+    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
     const float *X = A;
@@ -301,8 +301,8 @@ hipError_t run_fp32_window(const Workspace &ws, const float *A, int n, const uin
                            int G, int result, int nbA, float *out, double *log2_scale,
                            hipStream_t s, TimingSink *timing) {
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n);
-    if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
+    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
     const float *mat[kSlots] = {A, ws.wp[0], ws.wp[1], ws.wp[2], ws.wp[3], ws.buf[0], ws.buf[1]};
@@ -377,8 +377,8 @@ hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64
     MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
     if (p == 1) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n);
-    if (!vec4 && kernel == MPOW_KERNEL_GEMM_F32_256) kernel = MPOW_KERNEL_GEMM_F32_128;
+    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
     const int G = (int)(p - 1);

@@ -51,14 +51,18 @@ MPOW_KERNEL_GEMM_F32_64_K2 = 11
 MPOW_KERNEL_GEMM_F32_128_K2 = 12
 MPOW_KERNEL_GEMM_BF16X6_128 = 13
 MPOW_KERNEL_GEMM_BF16X6_256 = 14
-MPOW_KERNEL_COUNT = 16
+MPOW_KERNEL_GEMM_F32_64_DMA = 15
+MPOW_KERNEL_GEMM_F32_128_DMA = 16
+MPOW_KERNEL_GEMM_F32_256x128_DMA = 17
+MPOW_KERNEL_COUNT = 18
 
 # every symbol include/mpow.h declares
 EXPORTS = (
     "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_window_schedule", "mpow_workspace_bytes",
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched", "mpow_expm",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
-    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_mode_for_tolerance",
+    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_fp32_kernel_for",
+    "mpow_mode_for_tolerance",
     "mpow_srv_create", "mpow_srv_submit", "mpow_srv_poll", "mpow_srv_wait_idle", "mpow_srv_stats",
     "mpow_srv_destroy", "mpow_srv_simulate",
 )
@@ -120,6 +124,7 @@ def _load():
     sig = {
         "mpow_status_str": (c.c_char_p, [c.c_int]),
         "mpow_gemm_count": (c.c_int, [c.c_int64]),
+        "mpow_fp32_kernel_for": (c.c_int, [c.c_int, c.c_int]),
         "mpow_schedule": (c.c_int, [c.c_int64, P, c.c_int]),
         "mpow_window_schedule": (c.c_int, [c.c_int64, c.c_int, P, c.c_int, c.POINTER(c.c_int)]),
         "mpow_workspace_bytes": (c.c_size_t, [c.c_int, c.c_int, c.c_int]),
@@ -167,6 +172,11 @@ def mpow_status_str(status: int) -> str:
 
 def mpow_gemm_count(p: int) -> int:
     return int(_load().mpow_gemm_count(int(p)))
+
+
+def mpow_fp32_kernel_for(n: int, aligned: bool = True) -> int:
+    """The float32 product kernel id mpow_run uses at size n by default."""
+    return int(_load().mpow_fp32_kernel_for(int(n), 1 if aligned else 0))
 
 
 def mpow_schedule(p: int) -> list:

@@ -175,3 +175,22 @@ def test_window_schedule_counts_and_rejects(lib):
     assert lib.mpow_window_schedule(5, 1, None, 0, None) == -1
     buf = (ctypes.c_uint8 * 3)()
     assert lib.mpow_window_schedule(1023, 1, ctypes.cast(buf, ctypes.c_void_p), 1, ctypes.byref(r)) == -1
+
+
+def test_fp32_kernel_for_default_choice():
+    # Host-side default product kernel per size: K-split tiles below 768, then
+    # the LDS-DMA tile whose tile count best fills whole waves of 256 CUs
+    # (16-byte loads), the register-staged tiles otherwise.
+    k = mpow.mpow_fp32_kernel_for
+    assert k(0) == -1 and k(-5) == -1
+    assert k(1) == k(512) == k(767) == mpow.MPOW_KERNEL_GEMM_F32_32_K4
+    assert k(768) == k(1024) == k(1536) == k(3072) == mpow.MPOW_KERNEL_GEMM_F32_64_DMA
+    assert k(2048) == k(6144) == mpow.MPOW_KERNEL_GEMM_F32_128_DMA
+    assert k(2600) == k(4096) == k(8192) == mpow.MPOW_KERNEL_GEMM_F32_256x128_DMA
+    # beyond a 32-bit buffer range: the register-staged 256 x 256 tile
+    assert k(23170) != mpow.MPOW_KERNEL_GEMM_F32_256 and k(23172) == mpow.MPOW_KERNEL_GEMM_F32_256
+    # no 16-byte loads: same-order or K-split register-staged tiles
+    assert k(1000, False) == mpow.MPOW_KERNEL_GEMM_F32_64_K2
+    assert k(2048, False) == mpow.MPOW_KERNEL_GEMM_F32_128_K2
+    assert k(3000, False) == mpow.MPOW_KERNEL_GEMM_F32_64
+    assert k(8192, False) == mpow.MPOW_KERNEL_GEMM_F32_128

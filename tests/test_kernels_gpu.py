@@ -13,11 +13,15 @@ from gpu_util import check_against_oracle, run_gpu, tol_mode
 
 pytestmark = pytest.mark.gpu
 
+DMA = [mpow.MPOW_KERNEL_GEMM_F32_256, mpow.MPOW_KERNEL_GEMM_F32_64_DMA, mpow.MPOW_KERNEL_GEMM_F32_128_DMA,
+       mpow.MPOW_KERNEL_GEMM_F32_256x128_DMA]
 SAME_ORDER = [mpow.MPOW_KERNEL_GEMM_F32_128, mpow.MPOW_KERNEL_GEMM_F32_64, mpow.MPOW_KERNEL_GEMM_F32_32,
-              mpow.MPOW_KERNEL_GEMM_F32_256, mpow.MPOW_KERNEL_GEMM_F32_128x64]
+              mpow.MPOW_KERNEL_GEMM_F32_128x64] + DMA
 K_SPLIT = [mpow.MPOW_KERNEL_GEMM_F32_32_K4, mpow.MPOW_KERNEL_GEMM_F32_32_K8,
            mpow.MPOW_KERNEL_GEMM_F32_64_K2, mpow.MPOW_KERNEL_GEMM_F32_128_K2]
-SIZES = [1, 33, 100, 257, 300, 513, 1030]
+# the LDS-DMA tiles run where n % 4 == 0 (100, 300, 700, 1028), the others
+# fall back to a same-order tile
+SIZES = [1, 33, 100, 257, 300, 513, 700, 1028, 1030]
 
 
 @pytest.fixture(scope="module")
@@ -47,20 +51,21 @@ def test_same_order_kernels_bit_identical(fplan, n):
         assert err <= tol, (n, p, err, tol)
 
 
-@pytest.mark.parametrize("n", [300, 1030])
-def test_256_tile_operand_scale_paths(fplan, n):
-    # The 256 x 256 tile applies the operand scales 2^-eX, 2^-eY to its sums
+@pytest.mark.parametrize("kernel", DMA)
+@pytest.mark.parametrize("n", [300, 1028])
+def test_dma_tile_operand_scale_paths(fplan, kernel, n):
+    # The LDS-DMA tiles apply the operand scales 2^-eX, 2^-eY to their sums
     # when eX + eY keeps the unscaled product in the normal range, else to the
     # operands.  Inputs scaled by 2^k (exact) push the first product onto the
     # second path: M must be bit-identical to the unscaled run's, s shifted by
     # exactly k p, and both must equal the 128 x 128 tile's bits.
     A = inputs.gaussian(n, 900 + n)
     for p in (2, 17):
-        M0, s0 = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_256, A, p)
+        M0, s0 = forced(fplan, kernel, A, p)
         for k in (70, -40, -70):
             Ak = np.ldexp(A, k).astype(np.float32)
             assert np.array_equal(np.ldexp(Ak, -k), A)
-            M, s = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_256, Ak, p)
+            M, s = forced(fplan, kernel, Ak, p)
             assert s == s0 + k * p and np.array_equal(M, M0), (n, p, k)
             M1, s1 = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_128, Ak, p)
             assert s1 == s and np.array_equal(M1, M), (n, p, k)
@@ -118,7 +123,7 @@ def test_set_kernel_rejects_other_modes():
     h = mpow.mpow_plan_create(0, 64, 0, mpow.MPOW_FP32, 0)
     try:
         for bad in (-2, mpow.MPOW_KERNEL_GEMM_F16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256,
-                    mpow.MPOW_KERNEL_GEMM_BF16X6_128, 15, 99):
+                    mpow.MPOW_KERNEL_GEMM_BF16X6_128, mpow.MPOW_KERNEL_COUNT, 99):
             with pytest.raises(mpow.MpowError):
                 mpow.mpow_plan_set_kernel(h, bad)
     finally:
