@@ -95,6 +95,31 @@ def oracle_leg(cases, results, seconds_budget: float = 20.0):
     return cpu, errs
 
 
+def oracle_one_core(cases, seconds_budget: float = 5.0):
+    """The same oracle on one host core (BLAS limited to one thread), over the
+    benchmark's cases up to N = 2048, smallest first, until about
+    `seconds_budget` seconds."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from paper_1204_3052_amd import inputs
+
+    flop, spent, done = 0.0, 0.0, []
+    with threadpool_limits(limits=1, user_api="blas"):
+        for n, p in sorted(c for c in cases if c[0] <= 2048):
+            A = inputs.gaussian(n, 1)
+            t = time.perf_counter()
+            oracle.mpow_binary(A, p)
+            spent += time.perf_counter() - t
+            flop += gemm_count(p) * 2.0 * n ** 3
+            done.append(f"N={n} p={p}")
+            if spent > seconds_budget:
+                break
+    return {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle binary exponentiation on one core on " + ", ".join(done)
+                      + f"; {spent:.1f} s"}
+
+
 def split_workload(args):
     """FP32 vs the split-precision modes on N=4096, p in {64, 1000}.  Same
     effective-flop formula for every mode (G(p) 2N^3); the split modes also
@@ -250,10 +275,10 @@ def batched_workload(args):
         ms = float(np.median(times))
         res[name] = {"ms": round(ms, 3), "gflops": round(flop / ms / 1e6, 1),
                      "pct_fp32_mfma_peak": round(flop / ms / 1e6 / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2)}
-    mpow.mpow_plan_destroy(hb)
-    mpow.mpow_plan_destroy(hp)
     batched()  # the tuned batch once more: its results for the error sample
     torch.cuda.synchronize(dev)
+    mpow.mpow_plan_destroy(hb)
+    mpow.mpow_plan_destroy(hp)
     rng = np.random.default_rng(1)
     kept = {}
     for i in sorted(int(x) for x in rng.choice(count, 32, replace=False)):
@@ -296,10 +321,14 @@ def serving_workload(args):
     slots = 256
     out = torch.empty((slots, 2048 * 2048), dtype=torch.float32, device=dev)
     scale = torch.zeros(slots, dtype=torch.float64, device=dev)
-    # a stratified sample (by size) kept in its own buffers for the error check
+    # a stratified sample (size bucket x mode, 200 requests) kept in its own
+    # buffers for the error check; fewer of the costly n >= 1024 requests
     rng = np.random.default_rng(0)
-    small_idx = np.flatnonzero(ns <= 512)
-    sample = set(int(i) for i in rng.choice(small_idx, min(24, len(small_idx)), replace=False))
+    sample = set()
+    for lo, hi, k in STRATA:
+        for m in (mpow.MPOW_FP32, mpow.MPOW_BF16X3):
+            idx = np.flatnonzero((ns >= lo) & (ns < hi) & (modes == m))
+            sample.update(int(i) for i in rng.choice(idx, min(k, len(idx)), replace=False))
     samp_out = {i: torch.empty((int(ns[i]), int(ns[i])), device=dev) for i in sample}
     samp_scale = torch.zeros(count, dtype=torch.float64, device=dev)
     budget = 16 << 30
@@ -384,9 +413,28 @@ def serving_workload(args):
         "span_s": round(span, 3), "wall_s": round(wall, 3), "backpressure_waits": backpressure,
         "arena_peak_bytes": int(stats["arena_peak"]), "arena_budget_bytes": budget,
         "plain_fifo_baseline": fifo,
-        "sample_errors": errs, "sample_within_tol": all(e["within_tol"] for e in errs),
+        "sample_check": sample_summary(errs),
         "cpu_baseline": cpu}), flush=True)
     return 0
+
+
+# serving's error sample: (n from, n below, requests per mode)
+STRATA = ((32, 128, 22), (128, 256, 22), (256, 512, 22), (512, 1024, 22), (1024, 2049, 12))
+
+
+def sample_summary(errs):
+    """Per size bucket and mode: count and the largest error / tolerance;
+    overall: whether every sampled result is within its tolerance, and the
+    five closest to their tolerance."""
+    out = {"requests": len(errs), "within_tol": all(e["within_tol"] for e in errs), "strata": {}}
+    for lo, hi, _ in STRATA:
+        for mode in ("fp32", "bf16x3"):
+            sel = [e for e in errs if lo <= e["n"] < hi and e["mode"] == mode]
+            if sel:
+                out["strata"][f"n{lo}-{hi - 1}_{mode}"] = {
+                    "count": len(sel), "max_err_over_tol": round(max(e["rel_err"] / e["tol"] for e in sel), 4)}
+    out["closest"] = sorted(errs, key=lambda e: -e["rel_err"] / e["tol"])[:5]
+    return out
 
 
 def sample_oracle_leg(kept):
@@ -835,6 +883,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu, errs = oracle_leg(cases, kept)
         result["cpu_baseline"] = cpu
+        result["cpu_baseline_one_core"] = oracle_one_core(cases)
         for c in per_case:
             e = errs.get((c["n"], c["p"]))
             c["rel_err"] = float(f"{e[0]:.3e}") if e else None

@@ -144,7 +144,6 @@ hipError_t launch_variant(const GemmLaunch &g, bool vec4, bool axpi, hipStream_t
 int gemm_pick(int n, bool vec4) {
     if (n < 768) return MPOW_KERNEL_GEMM_F32_32_K4;
     if (vec4 && n <= DMA_MAX_N) {
-        constexpr int kCUs = 256;
         struct Cand {
             int id, bm, bn;
             double rate;  // TFLOP/s with whole waves of tiles
@@ -158,9 +157,7 @@ int gemm_pick(int n, bool vec4) {
         int best = MPOW_KERNEL_GEMM_F32_64_DMA;
         double best_rate = 0.0;
         for (const Cand &c : cands) {
-            const double T = (double)((n + c.bm - 1) / c.bm) * (double)((n + c.bn - 1) / c.bn);
-            const double waves = (double)(int64_t)((T + kCUs - 1) / kCUs);
-            const double rate = c.rate * (T / kCUs) / waves;
+            const double rate = tile_fill_rate(c.rate, n, c.bm, c.bn);
             if (rate > best_rate) {
                 best_rate = rate;
                 best = c.id;

@@ -154,6 +154,15 @@ const char *gemm_split_name(int kernel);
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s);
 
 // Float32 product kernel variants (index = MPOW_KERNEL_* id).
+// Estimated rate of a tile shape for an n x n product: `rate`, its rate when
+// every one of the 256 CUs runs whole waves of tiles, times the filled
+// fraction of the last wave of workgroups, (T / 256) / ceil(T / 256) for T
+// output tiles of bm x bn.
+inline double tile_fill_rate(double rate, int n, int bm, int bn) {
+    const double T = (double)((n + bm - 1) / bm) * (double)((n + bn - 1) / bn);
+    const double waves = (double)(int64_t)((T + 255.0) / 256.0);
+    return rate * (T / 256.0) / waves;
+}
 int gemm_pick(int n, bool vec4);            // default kernel id for size n
 bool gemm_is_f32(int kernel);
 int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)

@@ -285,6 +285,180 @@ hipError_t launch_gemm_split(const SplitGemmLaunch &g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The same product with its operand tiles moved by LDS-DMA buffer loads
+// (global -> LDS without VGPRs; lane l of a load lands at byte 16 l of a
+// 1 KB LDS window).  The parts are zero-padded ld x ld arrays, so a tile
+// never needs a bounds check, and the K advance is the loads' scalar offset.
+// LDS rows are unpadded (SBK 16-bit elements); 16-byte chunk c of row r sits
+// at chunk position c ^ swz(r), which spreads the rows that share LDS banks
+// (rows r + 16/CPR apart) over distinct positions, so the 16-byte operand
+// reads are conflict-free.  Without padding a 256 x 256 tile with SBK = 32
+// fits LDS twice (double buffer), halving the barriers of the SBK = 16
+// register-staged tile.  Products per 16-wide K chunk in the same order as
+// gemm_split_kernel: bit-identical results.  Needs ld <= kSplitDmaMaxLd.
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK>
+__global__ __launch_bounds__(WM *WN * 64) void gemm_split_dma_kernel(SplitGemmLaunch g) {
+    typedef SplitTraits<T> Tr;
+    typedef typename Vec8<T>::type V8;
+    constexpr int NT = WM * WN * 64, NW = NT / 64;
+    constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
+    constexpr int CPR = SBK / 8;   // 16-byte chunks per tile row
+    constexpr int RPS = 64 / CPR;  // tile rows per 1 KB load
+    constexpr int A_PER = BM / RPS / NW, B_PER = BN / RPS / NW;  // loads per wave and part
+    static_assert(A_PER * NW * RPS == BM && B_PER * NW * RPS == BN && A_PER > 0 && B_PER > 0,
+                  "loads");
+    // two buffers as separate arrays, so the compiler sees that the loads
+    // into one do not alias the operand reads from the other
+    __shared__ __attribute__((aligned(16))) T A0[NP][BM * SBK];
+    __shared__ __attribute__((aligned(16))) T A1[NP][BM * SBK];
+    __shared__ __attribute__((aligned(16))) T B0[NP][BN * SBK];
+    __shared__ __attribute__((aligned(16))) T B1[NP][BN * SBK];
+    __shared__ double red[NW];
+
+    const int n = g.n, ld = g.ld;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN, grp = lane >> 5, l32 = lane & 31;
+    int tm, tn;
+    tile_of_block(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    auto swz = [](int row) { return (row / (16 / CPR)) % CPR; };
+    typedef __attribute__((address_space(3))) void lds_void;
+    const int bytes = ld * ld * 2;
+    __amdgpu_buffer_rsrc_t rx[NP], ry[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        rx[k] = __builtin_amdgcn_make_buffer_rsrc((void *)g.x[k], (short)0, bytes, 0x00020000);
+        ry[k] = __builtin_amdgcn_make_buffer_rsrc((void *)g.y[k], (short)0, bytes, 0x00020000);
+    }
+    unsigned a_off[A_PER], b_off[B_PER];
+#pragma unroll
+    for (int r = 0; r < A_PER; ++r) {
+        const int row = RPS * (wave + r * NW) + lane / CPR;
+        a_off[r] = (unsigned)(((m0 + row) * ld + 8 * ((lane % CPR) ^ swz(row))) * 2);
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER; ++r) {
+        const int row = RPS * (wave + r * NW) + lane / CPR;
+        b_off[r] = (unsigned)(((n0 + row) * ld + 8 * ((lane % CPR) ^ swz(row))) * 2);
+    }
+    auto load_tile = [&](int k0, T (*as)[BM * SBK], T (*bs)[BN * SBK]) {
+        const unsigned so = (unsigned)(k0 * 2);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r) {
+                const unsigned off = a_off[r];
+                const __amdgpu_buffer_rsrc_t rr = rx[k];
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rr, (lds_void *)(as[k] + (wave + r * NW) * 512), 16, off, so, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < B_PER; ++r) {
+                const unsigned off = b_off[r];
+                const __amdgpu_buffer_rsrc_t rr = ry[k];
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rr, (lds_void *)(bs[k] + (wave + r * NW) * 512), 16, off, so, 0, 0);
+            }
+        }
+    };
+
+    v16f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 256).
+    const int nk = (n + SBK - 1) / SBK;
+    auto body = [&](int kt, T (*as)[BM * SBK], T (*bs)[BN * SBK], T (*an)[BM * SBK],
+                    T (*bn)[BN * SBK]) {
+        if (kt + 1 < nk) load_tile((kt + 1) * SBK, an, bn);
+#pragma unroll
+        for (int s = 0; s < SBK / 16; ++s) {
+            V8 a[NP][FM], b[NP][FN];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int row = wm * TM + i * 32 + l32;
+                    a[k][i] = *(const V8 *)(&as[k][row * SBK + 8 * ((2 * s + grp) ^ swz(row))]);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int row = wn * TN + j * 32 + l32;
+                    b[k][j] = *(const V8 *)(&bs[k][row * SBK + 8 * ((2 * s + grp) ^ swz(row))]);
+                }
+            }
+            // the fixed product order of gemm_split_kernel
+#pragma unroll
+            for (int d = 0; d < NP; ++d)
+#pragma unroll
+                for (int u = 0; u <= d; ++u)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = mfma16<T>(a[u][i], b[d - u][j], acc[i][j]);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the next tile is in LDS
+        __syncthreads();
+    };
+    load_tile(0, A0, B0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+        body(kt, A0, B0, A1, B1);
+        if (kt + 1 < nk) body(kt + 1, A1, B1, A0, B0);
+    }
+
+    // C = acc * 2^-2k, an exact power of two.
+    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
+    double ss = 0.0;
+    float *__restrict__ C = g.C;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
+                const int col = n0 + wn * TN + j * 32 + l32;
+                const float v = acc[i][j][r] * outScale;
+                if (row < n && col < n) {
+                    C[(int64_t)row * n + col] = v;
+                    ss += (double)v * (double)v;
+                }
+            }
+    ss = wave_sum_lane0(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w];
+        g.partC[blockIdx.x] = t;
+    }
+}
+
+// Largest ld whose ld x ld 16-bit part a 32-bit buffer offset covers
+// (a multiple of 256 with ld^2 * 2 < 2^31).
+constexpr int kSplitDmaMaxLd = 32512;
+
+// The LDS-DMA kernel when the padded parts fit a buffer's range, else the
+// register-staged one of the same tile (same results either way).
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int DWM, int DWN,
+          int DSBK>
+hipError_t launch_split_product(const SplitGemmLaunch &g, hipStream_t s) {
+    if (g.ld > kSplitDmaMaxLd) return launch_gemm_split<T, NP, BM, BN, WM, WN, SBK>(g, s);
+    const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_split_dma_kernel<T, NP, BM, BN, DWM, DWN, DSBK>), dim3(tiles),
+                       dim3(DWM * DWN * 64), 0, s, g);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int split_parts(int mode) { return mode == MPOW_BF16X6 ? 3 : (mode == MPOW_FP32 ? 0 : 2); }
@@ -306,16 +480,18 @@ hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
     return hipGetLastError();
 }
 
-// 256 x 256 tiles (8 waves, each 128 x 64, K tile 16) from this size up:
-// twice the MFMA work per LDS byte of the 128 x 128 tile.  Both accumulate
-// every output in the same order (per 16-wide K chunk, the fixed product
-// order above), so the two give bit-identical results.
-constexpr int kSplit256From = 2048;
-
+// 256 x 256 or 128 x 128 tiles, whichever has the higher estimated rate for
+// how its tile count fills the CUs (tile_fill_rate), with full-wave rates
+// measured on MI355X (16-bit MFMA TFLOP/s, LDS-DMA kernels): X3 modes
+// 256 x 256 1160, 128 x 128 1009; BF16X6 1228 and 1137.  Both accumulate every
+// output in the same order (per 16-wide K chunk, the fixed product order
+// above), so the two give bit-identical results.
 int gemm_split_pick(int mode, int n) {
-    const bool big = n >= kSplit256From;
+    const bool x6 = mode == MPOW_BF16X6;
+    const bool big = tile_fill_rate(x6 ? 1228.0 : 1160.0, n, 256, 256) >
+                     tile_fill_rate(x6 ? 1137.0 : 1009.0, n, 128, 128);
     if (mode == MPOW_FP16X3) return big ? MPOW_KERNEL_GEMM_F16X3_256 : MPOW_KERNEL_GEMM_F16X3_128;
-    if (mode == MPOW_BF16X6) return big ? MPOW_KERNEL_GEMM_BF16X6_256 : MPOW_KERNEL_GEMM_BF16X6_128;
+    if (x6) return big ? MPOW_KERNEL_GEMM_BF16X6_256 : MPOW_KERNEL_GEMM_BF16X6_128;
     return big ? MPOW_KERNEL_GEMM_BF16X3_256 : MPOW_KERNEL_GEMM_BF16X3_128;
 }
 
@@ -346,24 +522,31 @@ int gemm_split_tiles(int kernel, int n) {
 
 const char *gemm_split_name(int kernel) {
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_kernel<_Float16,2,128,128,2,2,32>";
-        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_kernel<__bf16,2,128,128,2,2,32>";
-        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_kernel<_Float16,2,256,256,2,4,16>";
-        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_kernel<__bf16,2,256,256,2,4,16>";
-        case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_kernel<__bf16,3,128,128,2,2,32>";
-        case MPOW_KERNEL_GEMM_BF16X6_256: return "gemm_split_kernel<__bf16,3,256,256,2,4,16>";
+        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_dma_kernel<_Float16,2,128,128,2,4,64>";
+        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_dma_kernel<__bf16,2,128,128,2,4,64>";
+        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_dma_kernel<_Float16,2,256,256,2,4,32>";
+        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_dma_kernel<__bf16,2,256,256,2,4,32>";
+        case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_dma_kernel<__bf16,3,128,128,2,4,32>";
+        case MPOW_KERNEL_GEMM_BF16X6_256: return "gemm_split_dma_kernel<__bf16,3,256,256,2,4,16>";
         default: return nullptr;
     }
 }
 
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s) {
+    // register-staged tile <BM, BN, WM, WN, SBK>, then the LDS-DMA waves and K tile
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F16X3_128: return launch_gemm_split<_Float16, 2, 128, 128, 2, 2, 32>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X3_128: return launch_gemm_split<__bf16, 2, 128, 128, 2, 2, 32>(g, s);
-        case MPOW_KERNEL_GEMM_F16X3_256: return launch_gemm_split<_Float16, 2, 256, 256, 2, 4, 16>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X3_256: return launch_gemm_split<__bf16, 2, 256, 256, 2, 4, 16>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X6_128: return launch_gemm_split<__bf16, 3, 128, 128, 2, 2, 32>(g, s);
-        case MPOW_KERNEL_GEMM_BF16X6_256: return launch_gemm_split<__bf16, 3, 256, 256, 2, 4, 16>(g, s);
+        case MPOW_KERNEL_GEMM_F16X3_128:
+            return launch_split_product<_Float16, 2, 128, 128, 2, 2, 32, 2, 4, 64>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_128:
+            return launch_split_product<__bf16, 2, 128, 128, 2, 2, 32, 2, 4, 64>(g, s);
+        case MPOW_KERNEL_GEMM_F16X3_256:
+            return launch_split_product<_Float16, 2, 256, 256, 2, 4, 16, 2, 4, 32>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X3_256:
+            return launch_split_product<__bf16, 2, 256, 256, 2, 4, 16, 2, 4, 32>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X6_128:
+            return launch_split_product<__bf16, 3, 128, 128, 2, 2, 32, 2, 4, 32>(g, s);
+        case MPOW_KERNEL_GEMM_BF16X6_256:
+            return launch_split_product<__bf16, 3, 256, 256, 2, 4, 16, 2, 4, 16>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
