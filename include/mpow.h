@@ -216,12 +216,14 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
 /* Tile table of the batched kernel: table[b] is the tile shape used for
  * matrices with n in (16(b-1), 16b], b = 1..16 (table[0] is unused); shapes
  * 0 = 128x128, 1 = 64x64, 2 = 256x256 on 8 waves.  Every shape gives
- * bit-identical results; only speed differs.  A batch runs on one of three
- * kernel instances: the smallest that holds every shape it uses (without
- * shape 0 or 2: a 64x64-only instance that keeps four workgroups per CU;
- * with shape 2: an instance of one 8-wave workgroup per CU, fastest for
- * batches of large matrices, e.g. n = 256 at 100 against 75 TFLOP/s, but
- * slower for mixed batches, so the autotuner picks only shapes 0 and 1).
+ * bit-identical results; only speed differs.  A batch runs on one kernel
+ * instance: the smallest that holds every shape it uses (without shape 0
+ * or 2: a 64x64-only instance that keeps four workgroups per CU; with
+ * shape 2: an instance of one 8-wave workgroup per CU); with shape 0 and
+ * every matrix allowing 16-byte loads (n % 4 == 0, 16-byte aligned A), an
+ * instance whose 128x128 and 64x64 tiles load straight into LDS (e.g.
+ * n = 256 at 100 against 73 TFLOP/s).  The autotuner picks among shapes 0
+ * and 1, timed on that instance.
  * set = 0 copies the plan's table into table[0..16]; set = 1 replaces it.
  * len must be >= 17.
  * Errors: INVALID (plan NULL or without batch support, len < 17, a shape

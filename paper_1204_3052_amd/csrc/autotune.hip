@@ -156,6 +156,9 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
         float best = 1e30f;
         int best_shape = plan->batch.cfg[b];
         for (int shape = 0; shape < kTunedShapes && st == MPOW_SUCCESS; ++shape) {
+            // timed on the instance a mixed batch of 16-byte-loadable matrices
+            // runs on (the buffers here are 16-byte aligned, n a multiple of 16)
+            const int inst = batch_instance(1, true);
             float t_min = 1e30f;
             for (int rep = 0; rep < 4 && st == MPOW_SUCCESS; ++rep) {
                 hdr->counter = 0;
@@ -171,7 +174,7 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                 float ms = 0.f;
                 if (hipMemcpyAsync(plan->batch.slot[0].desc, plan->batch.slot[0].host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
                     hipEventRecord(e0, s) != hipSuccess ||
-                    launch_batched(bl, plan->batch.workers[shape == 0 ? 1 : 0], shape == 0 ? 1 : 0, s) != hipSuccess ||
+                    launch_batched(bl, plan->batch.workers[inst], inst, s) != hipSuccess ||
                     hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                     st = MPOW_ERR_DEVICE;

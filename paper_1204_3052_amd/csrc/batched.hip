@@ -18,8 +18,13 @@
 // holds only the 64x64 tile (124 registers, four workgroups per CU),
 // instance 1 the 128x128 and 64x64 tiles (244 registers, two per CU), and
 // instance 2 the 256x256 tile on 8 waves (one per CU).  The host launches the
-// smallest instance that holds every tile shape the batch uses.
+// smallest instance that holds every tile shape the batch uses.  A fourth
+// instance, for batches whose every matrix allows 16-byte loads (n % 4 == 0,
+// 16-byte aligned A), runs the 128x128 and 64x64 shapes as the LDS-DMA tiles
+// of gemm_f32_dma.h (the same accumulation order, so the same bits wherever
+// nothing is subnormal) in place of instance 1.
 #include "mpow_internal.h"
+#include "gemm_f32_dma.h"
 #include "gemm_f32_tile.h"
 
 namespace mpow {
@@ -163,6 +168,29 @@ __device__ __forceinline__ double wg_product(const float *X, int eX, const float
     return S;
 }
 
+// The same product with the LDS-DMA tile (16-byte loads, n <= 256).
+template <int BM, int BN, int WM, int WN, int BK>
+__device__ __forceinline__ double wg_product_dma(const float *X, int eX, const float *Y, int eY,
+                                                 float *C, int n, float *As0, float *As1,
+                                                 float *Bs0, float *Bs1, double *red,
+                                                 double *bcast) {
+    const int tn = (n + BN - 1) / BN, tm = (n + BM - 1) / BM;
+    auto exps = [&]() { return OperandExps{eX, eY}; };
+    double S = 0.0;
+    for (int t = 0; t < tm * tn; ++t) {
+        int nn = n, m0 = (t / tn) * BM, n0 = (t % tn) * BN;
+        asm volatile("" : "+s"(nn), "+s"(m0), "+s"(n0), "+s"(X), "+s"(Y), "+s"(C));
+        const double ts = f32_tile_dma<BM, BN, WM, WN, BK, false>(X, Y, exps, C, nn, m0, n0, As0,
+                                                                  As1, Bs0, Bs1, red);
+        S += ts;  // meaningful in thread 0
+    }
+    if (threadIdx.x == 0) *bcast = S;
+    __syncthreads();
+    S = *bcast;
+    __syncthreads();
+    return S;
+}
+
 // Tile shape ids: 0 = 128x128, 1 = 64x64 (both give bit-identical
 // products), 2 = 256x256 with 8 waves.  Instances: INST 0 holds only 64x64
 // (every cfg runs 64x64), INST 1 holds 128x128 and 64x64, INST 2 (512
@@ -182,16 +210,12 @@ struct BatchInst {
                   : F32TileLds<TB, TB>::B_FLOATS;
 };
 
-template <int INST>
-__global__ __launch_bounds__(BatchInst<INST>::NT) void batched_kernel(BatchLaunch b) {
-    typedef BatchInst<INST> I;
-    constexpr int NT = I::NT;
-    __shared__ __attribute__((aligned(16))) float As[I::A_FLOATS];
-    __shared__ __attribute__((aligned(16))) float Bs[I::B_FLOATS];
-    __shared__ double red[NT];
-    __shared__ double bcast;
-    __shared__ int claimed;
-
+// The worker loop: claim matrices until the queue is empty and compute each
+// one's whole power; product(cfg, X, eX, Y, eY, C, n, vec) computes one
+// product in the workgroup and returns its sum of squares.
+template <int NT, typename ProductFn>
+__device__ __forceinline__ void run_jobs(const BatchLaunch &b, double *red, int *claimed,
+                                         ProductFn product) {
     BatchHeader *hdr = (BatchHeader *)b.desc;
     const BatchItem *items = (const BatchItem *)(hdr + 1);
     const int count = hdr->count;
@@ -199,9 +223,9 @@ __global__ __launch_bounds__(BatchInst<INST>::NT) void batched_kernel(BatchLaunc
     float *S1 = S0 + b.slot_floats;
 
     for (;;) {
-        if (threadIdx.x == 0) claimed = atomicAdd(&hdr->counter, 1);
+        if (threadIdx.x == 0) *claimed = atomicAdd(&hdr->counter, 1);
         __syncthreads();
-        const int it = claimed;
+        const int it = *claimed;
         __syncthreads();
         if (it >= count) break;
 
@@ -237,16 +261,7 @@ __global__ __launch_bounds__(BatchInst<INST>::NT) void batched_kernel(BatchLaunc
                     float *C = (k & 1) ? S1 : S0;
                     const float *Y = mul ? item.A : X;
                     const int eY = mul ? eA : eX;
-                    if (INST == 2) {
-                        if (item.cfg == 2)
-                            SX = wg_product<256, 256, 2, 4, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
-                        else
-                            SX = wg_product<128, 128, 2, 4, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
-                    } else if (INST == 1 && item.cfg == 0) {
-                        SX = wg_product<128, 128, 2, 2, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
-                    } else {
-                        SX = wg_product<64, 64, 2, 2, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
-                    }
+                    SX = product(item.cfg, X, eX, Y, eY, C, n, vec);
                     s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
                     X = C;
                     eX = exponent_of_sumsq(SX);
@@ -269,6 +284,51 @@ __global__ __launch_bounds__(BatchInst<INST>::NT) void batched_kernel(BatchLaunc
     }
 }
 
+template <int INST>
+__global__ __launch_bounds__(BatchInst<INST>::NT) void batched_kernel(BatchLaunch b) {
+    typedef BatchInst<INST> I;
+    constexpr int NT = I::NT;
+    __shared__ __attribute__((aligned(16))) float As[I::A_FLOATS];
+    __shared__ __attribute__((aligned(16))) float Bs[I::B_FLOATS];
+    __shared__ double red[NT];
+    __shared__ double bcast;
+    __shared__ int claimed;
+    auto product = [&](int cfg, const float *X, int eX, const float *Y, int eY, float *C, int n,
+                       bool vec) -> double {
+        if (INST == 2) {
+            if (cfg == 2)
+                return wg_product<256, 256, 2, 4, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+            return wg_product<128, 128, 2, 4, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+        }
+        if (INST == 1 && cfg == 0)
+            return wg_product<128, 128, 2, 2, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+        return wg_product<64, 64, 2, 2, 1>(X, eX, Y, eY, C, n, vec, As, Bs, red, &bcast);
+    };
+    run_jobs<NT>(b, red, &claimed, product);
+}
+
+// Instance 3: shapes 0 (128x128, K tile 32) and 1 (64x64, K tile 64) as
+// LDS-DMA tiles; every matrix of the batch must allow 16-byte loads.
+constexpr int kDmaInstFloats = 4096;  // per LDS buffer: 128 x 32 = 32 x 128 = 64 x 64
+__global__ __launch_bounds__(256) void batched_dma_kernel(BatchLaunch b) {
+    __shared__ __attribute__((aligned(16))) float As0[kDmaInstFloats];
+    __shared__ __attribute__((aligned(16))) float As1[kDmaInstFloats];
+    __shared__ __attribute__((aligned(16))) float Bs0[kDmaInstFloats];
+    __shared__ __attribute__((aligned(16))) float Bs1[kDmaInstFloats];
+    __shared__ double red[256];
+    __shared__ double bcast;
+    __shared__ int claimed;
+    auto product = [&](int cfg, const float *X, int eX, const float *Y, int eY, float *C, int n,
+                       bool) -> double {
+        if (cfg == 0)
+            return wg_product_dma<128, 128, 2, 2, 32>(X, eX, Y, eY, C, n, As0, As1, Bs0, Bs1, red,
+                                                      &bcast);
+        return wg_product_dma<64, 64, 2, 2, 64>(X, eX, Y, eY, C, n, As0, As1, Bs0, Bs1, red,
+                                                &bcast);
+    };
+    run_jobs<256>(b, red, &claimed, product);
+}
+
 }  // namespace
 
 // Default tile shape before tuning: the one that pads n least, larger on ties.
@@ -281,7 +341,9 @@ int batched_cfg_for(int n) {
 int batched_occupancy(int inst) {
     int blocks = 0;
     hipError_t e;
-    if (inst == 2)
+    if (inst == 3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_dma_kernel, 256, 0);
+    else if (inst == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<2>, 512, 0);
     else if (inst == 1)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<1>, 256, 0);
@@ -292,7 +354,9 @@ int batched_occupancy(int inst) {
 }
 
 hipError_t launch_batched(const BatchLaunch &b, int grid, int inst, hipStream_t s) {
-    if (inst == 2)
+    if (inst == 3)
+        hipLaunchKernelGGL(batched_dma_kernel, dim3(grid), dim3(256), 0, s, b);
+    else if (inst == 2)
         hipLaunchKernelGGL(batched_kernel<2>, dim3(grid), dim3(512), 0, s, b);
     else if (inst == 1)
         hipLaunchKernelGGL(batched_kernel<1>, dim3(grid), dim3(256), 0, s, b);

@@ -207,12 +207,16 @@ struct BatchLaunch {
 constexpr int kBatchMaxN = 256;
 constexpr int kTileBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
 constexpr int kBatchShapes = 3;   // tile shape ids of the batched kernel
-constexpr int kBatchInstances = 3;
+constexpr int kBatchInstances = 4;  // 0: 64x64; 1: 128x128 + 64x64; 2: 256x256; 3: LDS-DMA 128/64
 int batched_cfg_for(int n);
 // Resident workers per CU of kernel instance inst (0: 64x64 only, 1: 128x128
 // and 64x64, 2: 256x256 and 128x128 with 8 waves).
 int batched_occupancy(int inst);
 hipError_t launch_batched(const BatchLaunch &b, int grid, int inst, hipStream_t s);
+// Kernel instance for a batch: `need` = the smallest register-staged instance
+// holding every tile shape used (0, 1 or 2); all_vec = every matrix allows
+// 16-byte loads.
+int batch_instance(int need, bool all_vec);
 
 // One descriptor buffer of a batch context: device descriptors, the pinned
 // host copy the descriptor copy reads, a captured graph (copy + launch) and

@@ -471,6 +471,12 @@ hipError_t batch_wait_all(BatchContext *bc) {
     return hipSuccess;
 }
 
+int batch_instance(int need, bool all_vec) {
+    // the LDS-DMA instance replaces the 128x128 + 64x64 one when every matrix
+    // allows 16-byte loads
+    return (need == 1 && all_vec) ? 3 : need;
+}
+
 hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, const int *n,
                          const int64_t *p, float *const *out, double *const *scale,
                          hipStream_t s, bool use_graph, hipEvent_t *done) {
@@ -495,7 +501,8 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
     hdr->count = count;
     hdr->pad[0] = hdr->pad[1] = 0;
     BatchItem *items = (BatchItem *)(hdr + 1);
-    int inst = 0;  // the smallest kernel instance that holds every matrix's tile
+    int need = 0;  // the smallest kernel instance that holds every matrix's tile
+    bool all_vec = true;
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
         items[k].A = A[i];
@@ -504,9 +511,11 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         items[k].p = p[i];
         items[k].n = n[i];
         items[k].cfg = bc->cfg[(n[i] + 15) / 16];
-        const int need = items[k].cfg == 2 ? 2 : (items[k].cfg == 0 ? 1 : 0);
-        inst = need > inst ? need : inst;
+        const int nk = items[k].cfg == 2 ? 2 : (items[k].cfg == 0 ? 1 : 0);
+        need = nk > need ? nk : need;
+        all_vec = all_vec && n[i] % 4 == 0 && ((uintptr_t)A[i] & 15) == 0;
     }
+    const int inst = batch_instance(need, all_vec);
     const int grid = bc->workers[inst];
     // Batches share the workers' scratch: order this one after the previous
     // one even when it was enqueued on another stream.

@@ -91,6 +91,37 @@ def test_batched_equals_plain_bitwise(plans):
         assert np.array_equal(Mb, Mp) and sb == sp, (A.shape[0], p)
 
 
+# Every n a multiple of 4 (and the packed buffers 256-byte aligned): such a
+# batch runs on the LDS-DMA instance, which must give the plain path's bits,
+# also where an input's scale sends its first product down the operand-scaled
+# path (entries scaled by 2^70 and 2^-70).
+EDGE4_N = [4, 8, 12, 16, 20, 60, 64, 68, 100, 124, 128, 132, 192, 200, 252, 256]
+
+
+def edge4_batch(seed):
+    mats, ps = [], []
+    for i, n in enumerate(EDGE4_N):
+        for j, p in enumerate(EDGE_P):
+            A = inputs.gaussian(n, 1000 * seed + 7 * i + p)
+            if j % 3 == 1:
+                A = np.ldexp(A, 70 if i % 2 else -70).astype(np.float32)
+            mats.append(A)
+            ps.append(int(p))
+    order = np.random.default_rng(seed).permutation(len(mats))
+    return [mats[k] for k in order], [ps[k] for k in order]
+
+
+def test_batched_dma_instance_equals_plain_bitwise(plans):
+    hb, hp = plans
+    mats, ps = edge4_batch(4)
+    pk = Packed(mats)
+    run_batch(hb, pk, ps)
+    for i, (A, p) in enumerate(zip(mats, ps)):
+        Mb, sb = pk.result(i)
+        Mp, sp = run_gpu(hp, A, p)
+        assert np.array_equal(Mb, Mp) and sb == sp, (A.shape[0], p)
+
+
 def test_batched_nonlog_equals_plain(plans):
     hb, hp = plans
     mats, ps = edge_batch(2)
