@@ -258,11 +258,12 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
 mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel);
 
 /* The float32 product kernel (an MPOW_KERNEL_* id) that mpow_run uses at
- * size n when no kernel is forced: aligned != 0 means n % 4 == 0 and a
- * 16-byte aligned A (the LDS-DMA tiles need both).  Host-only, no device
- * call; -1 for n < 1.  Small n take K-split tiles; from n = 768 the LDS-DMA
- * tile with the best estimated rate for how its tile count fills the 256
- * CUs in whole waves (section 4.3.7's tiled product, tile size chosen per n). */
+ * size n when no kernel is forced: aligned != 0 means a 16-byte aligned A
+ * (the LDS-DMA tiles need that and n % 4 == 0).  Host-only, no device call;
+ * -1 for n < 1.  Below n = 768 the 32x32 tile with a 4-way K split (its
+ * whole-K-in-LDS form up to n = 512); from n = 768 the LDS-DMA tile with the
+ * best estimated rate for how its tile count fills the 256 CUs in whole
+ * waves (section 4.3.7's tiled product, tile size chosen per n). */
 int mpow_fp32_kernel_for(int n, int aligned);
 
 /* The last hipError_t value a call on this plan saw (0 if none). */
@@ -288,7 +289,8 @@ enum {
     MPOW_KERNEL_GEMM_F32_64_DMA = 15,  /* float32 product, 64x64 tiles, LDS-DMA loads, K tile 64 */
     MPOW_KERNEL_GEMM_F32_128_DMA = 16, /* float32 product, 128x128 tiles, 2x4 waves, LDS-DMA, K tile 64 */
     MPOW_KERNEL_GEMM_F32_256x128_DMA = 17, /* float32 product, 256x128 tiles, 4x2 waves, LDS-DMA */
-    MPOW_KERNEL_COUNT = 18
+    MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18, /* float32 product, 32x32 tiles, K split over 4 waves, whole K in LDS (n <= 512) */
+    MPOW_KERNEL_COUNT = 19
 };
 
 /* Timing of product launches recorded under MPOW_FLAG_TIMING since the last

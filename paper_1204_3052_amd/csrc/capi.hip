@@ -307,7 +307,8 @@ int mpow_mode_for_tolerance(double tol, double floor, int wide_range) {
 
 int mpow_fp32_kernel_for(int n, int aligned) {
     if (n < 1) return -1;
-    return gemm_resolve(gemm_pick(n, aligned != 0), n, aligned != 0);
+    const bool vec4 = aligned != 0 && n % 4 == 0;
+    return gemm_resolve(gemm_pick(n, vec4), n, vec4);
 }
 
 mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel) {

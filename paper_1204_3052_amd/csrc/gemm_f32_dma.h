@@ -260,3 +260,155 @@ __device__ __forceinline__ double f32_tile_dma(const float *__restrict__ X,
 }
 
 }  // namespace mpow
+
+namespace mpow {
+
+// Small n (n <= DMA_K4_MAX_N): one 32 x 32 output tile per workgroup, its K
+// range split over 4 waves, with the whole K range of both operand panels
+// (32 x n of X, n x 32 of Y) held in LDS.  At such n a K tile's MFMAs (16
+// per wave) take less time than its loads' memory latency, so a tile-by-tile
+// double buffer waits on memory at every step; here the loads run two stages
+// ahead (a stage = 128 values of K, its own LDS region, 8 LDS-DMA loads per
+// wave), one barrier per stage.  Wave w takes the 32-wide K slices w, w + 4,
+// w + 8, ... in ascending order and the four partial tiles are added in wave
+// order, as the register-staged 32 x 32 tile with a 4-way K split does, so
+// the two give the same bits (and the operand scales are applied as in
+// f32_tile_dma).  Layouts: a stage's X block is 32 rows of 128 floats, 16-byte
+// chunk c of row r at position c ^ (r & 15); its Y block is 128 rows of 32
+// floats, row k at float 32 k + 32 (k / 16) (a gap of 32 floats after every
+// 16 rows), so the lane halves' reads (rows k and k + 16) use different LDS
+// banks.
+constexpr int DMA_K4_MAX_N = 512;
+constexpr int DMA_K4_STAGES = DMA_K4_MAX_N / 128;
+constexpr int DMA_K4_A_STAGE = 32 * 128;       // floats of one stage's X block
+constexpr int DMA_K4_B_STAGE = 128 * 32 + 32 * 8;  // floats of one stage's Y block
+
+// All 256 threads must call it.  As[s] / Bs[s] (s < DMA_K4_STAGES) are
+// distinct LDS arrays of DMA_K4_A_STAGE / DMA_K4_B_STAGE floats (distinct so
+// that the compiler sees that a stage's loads do not alias the reads of the
+// stages before it and waits for no load it does not need).  Same
+// requirements and return value as f32_tile_dma, and n <= DMA_K4_MAX_N.
+template <bool AXPI, typename ExpFn>
+__device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
+                                                  const float *__restrict__ Y, ExpFn exps,
+                                                  float *__restrict__ C, int n, int m0, int n0,
+                                                  float *const *As, float *const *Bs,
+                                                  float alpha = 1.0f) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int h = lane >> 5, l32 = lane & 31;
+    const int bytes = n * n * 4;
+    const __amdgpu_buffer_rsrc_t rX =
+        __builtin_amdgcn_make_buffer_rsrc((void *)X, (short)0, bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rY =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Y, (short)0, bytes, 0x00020000);
+    constexpr unsigned OUT = 0x80000000u;
+    const int nst = (n + 127) / 128;  // stages
+    const int nsl = (n + 31) / 32;    // 32-wide K slices
+
+    // Stage s: X rows m0..m0+31, K [128 s, 128 s + 128) in 16 loads of 2 rows,
+    // Y rows 128 s ... in 16 loads of 8 rows; wave w issues loads 4w .. 4w+3
+    // of each.
+    auto load_stage = [&](int s) {
+        const int k0 = 128 * s;
+        float *as = As[s];
+        float *bs = Bs[s];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int u = 4 * wave + r;          // rows 2u, 2u + 1
+            const int row = 2 * u + (lane >> 5);
+            const int gc = k0 + 4 * ((lane & 31) ^ (row & 15));
+            const int gr = m0 + row;
+            const unsigned off = (gr < n && gc < n) ? (unsigned)((gr * n + gc) * 4) : OUT;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rX, (lds_void_t *)(as + u * 256), 16, off, 0,
+                                                     0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int g = 4 * wave + r;          // rows 8g .. 8g + 7
+            const int gr = k0 + 8 * g + (lane >> 3);
+            const int gc = n0 + 4 * (lane & 7);
+            const unsigned off = (gr < n && gc < n) ? (unsigned)((gr * n + gc) * 4) : OUT;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rY, (lds_void_t *)(bs + g * 256 + 32 * (g >> 1)), 16, off, 0, 0, 0);
+        }
+    };
+
+    // Every stage's loads at once (at most 128 KB per workgroup); one wait.
+#pragma unroll
+    for (int s = 0; s < DMA_K4_STAGES; ++s)
+        if (s < nst) load_stage(s);
+    const OperandExps e = exps();
+    const bool after = e.x + e.y >= -32 && e.x + e.y <= 96;  // scale in the epilogue
+    const PowScale fx = pow2_neg(e.x), fy = pow2_neg(e.y);
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's loads are in LDS
+    __syncthreads();
+
+    v16f acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < DMA_K4_STAGES; ++s) {
+        const int j = 4 * s + wave;  // this wave's slice of stage s
+        if (s < nst && j < nsl) {
+            const float *as = As[s];
+            const float *bs = Bs[s];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int cc = 8 * wave + 4 * h + q;  // chunk of this stage's 128 K
+                f4 a = *(const f4 *)(as + l32 * 128 + 4 * (cc ^ (l32 & 15)));
+                float b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 32 * wave + 16 * h + 4 * q + t;  // row of the Y block
+                    b[t] = bs[k * 32 + 32 * (k >> 4) + l32];
+                }
+                if (!after) {
+                    a = a * fx.a * fx.b;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) b[t] = b[t] * fy.a * fy.b;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[t], acc, 0, 0, 0);
+            }
+        }
+    }
+
+    // Waves 1..3 park their partial tiles in the first X block; wave 0 adds
+    // them in wave order.
+    float *park = As[0];
+    __syncthreads();
+    if (wave > 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) park[((wave - 1) * 16 + r) * 64 + lane] = acc[r];
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (wave == 0) {
+#pragma unroll
+        for (int g = 1; g < 4; ++g)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] += park[((g - 1) * 16 + r) * 64 + lane];
+        const PowScale fs = pow2_neg(after ? e.x + e.y : 0);
+        double ss = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + 8 * (r >> 2) + 4 * h + (r & 3);
+            const int col = n0 + l32;
+            if (row < n && col < n) {
+                float v = acc[r] * fs.a * fs.b;
+                if constexpr (AXPI) v = fmaf(v, alpha, row == col ? 1.0f : 0.0f);
+                C[(int64_t)row * n + col] = v;
+                ss += (double)v * (double)v;
+            }
+        }
+        ss = wave_sum_lane0(ss);
+        t = ss;  // valid in thread 0
+    }
+    __syncthreads();  // the LDS blocks may be reused by the caller
+    return t;
+}
+
+}  // namespace mpow

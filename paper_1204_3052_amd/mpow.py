@@ -54,7 +54,8 @@ MPOW_KERNEL_GEMM_BF16X6_256 = 14
 MPOW_KERNEL_GEMM_F32_64_DMA = 15
 MPOW_KERNEL_GEMM_F32_128_DMA = 16
 MPOW_KERNEL_GEMM_F32_256x128_DMA = 17
-MPOW_KERNEL_COUNT = 18
+MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18
+MPOW_KERNEL_COUNT = 19
 
 # every symbol include/mpow.h declares
 EXPORTS = (

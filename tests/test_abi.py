@@ -183,7 +183,9 @@ def test_fp32_kernel_for_default_choice():
     # (16-byte loads), the register-staged tiles otherwise.
     k = mpow.mpow_fp32_kernel_for
     assert k(0) == -1 and k(-5) == -1
-    assert k(1) == k(512) == k(767) == mpow.MPOW_KERNEL_GEMM_F32_32_K4
+    assert k(4) == k(300) == k(512) == mpow.MPOW_KERNEL_GEMM_F32_32_K4_DMA
+    assert k(1) == k(513) == k(516) == k(767) == mpow.MPOW_KERNEL_GEMM_F32_32_K4
+    assert k(300, False) == mpow.MPOW_KERNEL_GEMM_F32_32_K4
     assert k(768) == k(1024) == k(1536) == k(3072) == mpow.MPOW_KERNEL_GEMM_F32_64_DMA
     assert k(2048) == k(6144) == mpow.MPOW_KERNEL_GEMM_F32_128_DMA
     assert k(2600) == k(4096) == k(8192) == mpow.MPOW_KERNEL_GEMM_F32_256x128_DMA
