@@ -11,10 +11,11 @@
 // per-step Frobenius norm is a workgroup reduction and needs no extra launch.
 //
 // Tile shapes 128x128 and 64x64 (2x2 waves each) and 256x256 (2x4 waves),
-// one load path that picks 16- or 4-byte loads at run time, and three kernel
-// instances: every extra tile variant in a kernel raises its register
-// allocation (the compiler sizes it for the union of all paths), and with
-// eight variants in one kernel it reached one workgroup per CU.  Instance 0
+// one load path that picks 16- or 4-byte loads at run time, and three
+// register-staged kernel instances: every extra tile variant in a kernel
+// raises its register allocation (the compiler sizes it for the union of all
+// paths), and with eight variants in one kernel it reached one workgroup per
+// CU.  Instance 0
 // holds only the 64x64 tile (124 registers, four workgroups per CU),
 // instance 1 the 128x128 and 64x64 tiles (244 registers, two per CU), and
 // instance 2 the 256x256 tile on 8 waves (one per CU).  The host launches the

@@ -267,9 +267,10 @@ namespace mpow {
 // range split over 4 waves, with the whole K range of both operand panels
 // (32 x n of X, n x 32 of Y) held in LDS.  At such n a K tile's MFMAs (16
 // per wave) take less time than its loads' memory latency, so a tile-by-tile
-// double buffer waits on memory at every step; here the loads run two stages
-// ahead (a stage = 128 values of K, its own LDS region, 8 LDS-DMA loads per
-// wave), one barrier per stage.  Wave w takes the 32-wide K slices w, w + 4,
+// double buffer waits on memory at every step; here every load of the tile
+// is issued at once (stages of 128 values of K, each its own LDS region, 8
+// LDS-DMA loads per wave and stage), the tile waits once and then runs all
+// its MFMAs without a barrier.  Wave w takes the 32-wide K slices w, w + 4,
 // w + 8, ... in ascending order and the four partial tiles are added in wave
 // order, as the register-staged 32 x 32 tile with a 4-way K split does, so
 // the two give the same bits (and the operand scales are applied as in
@@ -283,11 +284,9 @@ constexpr int DMA_K4_STAGES = DMA_K4_MAX_N / 128;
 constexpr int DMA_K4_A_STAGE = 32 * 128;       // floats of one stage's X block
 constexpr int DMA_K4_B_STAGE = 128 * 32 + 32 * 8;  // floats of one stage's Y block
 
-// All 256 threads must call it.  As[s] / Bs[s] (s < DMA_K4_STAGES) are
-// distinct LDS arrays of DMA_K4_A_STAGE / DMA_K4_B_STAGE floats (distinct so
-// that the compiler sees that a stage's loads do not alias the reads of the
-// stages before it and waits for no load it does not need).  Same
-// requirements and return value as f32_tile_dma, and n <= DMA_K4_MAX_N.
+// All 256 threads must call it.  As[s] / Bs[s] (s < DMA_K4_STAGES) are LDS
+// arrays of DMA_K4_A_STAGE / DMA_K4_B_STAGE floats.  Same requirements and
+// return value as f32_tile_dma, and n <= DMA_K4_MAX_N.
 template <bool AXPI, typename ExpFn>
 __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
                                                   const float *__restrict__ Y, ExpFn exps,
