@@ -75,62 +75,91 @@ __device__ __forceinline__ v16f mfma16<__bf16>(b8 a, b8 b, v16f c) {
 
 constexpr int STS = 64;  // split tile edge
 
+// One 64 x 64 tile per workgroup.  The tile's float32 loads are issued before
+// the partial sums of squares are reduced, so the two latencies overlap.  A
+// thread holds two runs of 8 entries of one row (rows tid/8 and tid/8 + 32,
+// columns 8 (tid % 8) ...), writes their row-major parts as 16-byte stores
+// and the scaled floats to an LDS tile padded to 65 columns; it then reads 8
+// consecutive rows of one column (rows 8 (tid % 8) ..., columns tid/8 and
+// tid/8 + 32) and writes their transposed parts, again as 16-byte stores.
+// With the padding, the 64 lanes of a wave hit 64 distinct banks in both LDS
+// passes.  Every part is a function of the scaled entry alone, so both layouts
+// hold the same values.
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
     typedef SplitTraits<T> Tr;
-    typedef T V4 __attribute__((ext_vector_type(4)));
+    typedef typename Vec8<T>::type V8;
     __shared__ double red[256];
-    __shared__ T tp[NP][STS][STS + 8];  // the parts of the tile, for the transpose
+    __shared__ float tile[STS][STS + 1];
     const int tid = threadIdx.x;
     const int n = s.n, ld = s.ld;
+    const int r0 = blockIdx.y * STS, c0 = blockIdx.x * STS;
+    const bool vec = (n % 4) == 0 && ((uintptr_t)s.X & 15) == 0;
+    const int lr = tid / 8, lc = (tid % 8) * 8;
+
+    float v[2][8];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int gr = r0 + lr + 32 * q, gc = c0 + lc;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[q][t] = 0.f;
+        if (gr < n) {
+            const float *row = s.X + (int64_t)gr * n;
+            if (vec && gc + 7 < n) {
+                const f4 a = *(const f4 *)(row + gc), b = *(const f4 *)(row + gc + 4);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    v[q][t] = a[t];
+                    v[q][t + 4] = b[t];
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (gc + t < n) v[q][t] = row[gc + t];
+            }
+        }
+    }
+
     const int eX = exponent_of_sumsq(block_sum_partials<256>(s.part, s.nPart, red));
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && s.eSlot) *s.eSlot = eX;
     const PowScale f = pow2_neg(eX - Tr::kShift);
-    const int r0 = blockIdx.y * STS, c0 = blockIdx.x * STS;
-    const bool vec = (n % 4) == 0 && ((uintptr_t)s.X & 15) == 0;
 
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = tid / 16 + 16 * q, c = (tid % 16) * 4;
-        const int gr = r0 + r, gc = c0 + c;
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (gr < n) {
-            if (vec && gc + 3 < n) {
-                const f4 x = *(const f4 *)(s.X + (int64_t)gr * n + gc);
-                v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
-            } else {
+    for (int q = 0; q < 2; ++q) {
+        const int r = lr + 32 * q;
+        V8 pv[NP];
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (gc + t < n) v[t] = s.X[(int64_t)gr * n + gc + t];
-            }
-        }
-        V4 pv[NP];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float x = v[t] * f.a * f.b;
+        for (int t = 0; t < 8; ++t) {
+            float x = v[q][t] * f.a * f.b;
+            tile[r][lc + t] = x;
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 const T h = (T)x;
                 pv[k][t] = h;
-                tp[k][r][c + t] = h;
                 x = x - (float)h;  // exact: the rest of x after the first k + 1 parts
             }
         }
-        // four 16-bit values per 8-byte store (ld and gc are multiples of 4)
 #pragma unroll
-        for (int k = 0; k < NP; ++k) *(V4 *)((T *)s.rm[k] + (int64_t)gr * ld + gc) = pv[k];
+        for (int k = 0; k < NP; ++k) *(V8 *)((T *)s.rm[k] + (int64_t)(r0 + r) * ld + c0 + lc) = pv[k];
     }
     __syncthreads();
+    const int tr0 = (tid % 8) * 8;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = tid / 16 + 16 * q, r = (tid % 16) * 4;
+    for (int q = 0; q < 2; ++q) {
+        const int c = tid / 8 + 32 * q;
+        V8 pv[NP];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            V4 hv;
+        for (int t = 0; t < 8; ++t) {
+            float x = tile[tr0 + t][c];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) hv[t] = tp[k][r + t][c];
-            *(V4 *)((T *)s.tr[k] + (int64_t)(c0 + c) * ld + r0 + r) = hv;
+            for (int k = 0; k < NP; ++k) {
+                const T h = (T)x;
+                pv[k][t] = h;
+                x = x - (float)h;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < NP; ++k) *(V8 *)((T *)s.tr[k] + (int64_t)(c0 + c) * ld + r0 + tr0) = pv[k];
     }
 }
 
