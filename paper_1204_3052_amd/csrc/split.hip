@@ -472,19 +472,227 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_dma_kernel(SplitGemmLa
     }
 }
 
+// One 16-byte-per-lane buffer load into LDS (lane l's 16 bytes land at byte
+// lds + 16 l), written as assembly: the compiler then keeps no count of these
+// loads and inserts no waits for them, and the kernel that issues them waits
+// for them itself.  The LDS address goes through m0, which the sequence saves
+// and restores; one wait state separates the m0 write from the load that
+// reads it.  rsrc is a raw buffer descriptor (base, stride 0, num_records =
+// bytes, so an offset past the end reads zeros).
+__device__ __forceinline__ void lds_load16_asm(u4 rsrc, unsigned lds, unsigned voff,
+                                               unsigned soff) {
+    unsigned saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %1\n\t"
+        "s_nop 0\n\t"
+        "buffer_load_dwordx4 %2, %3, %4 offen lds\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "s"(lds), "v"(voff), "s"(rsrc), "s"(soff)
+        : "memory");
+}
+
+// vmcnt(N) alone (expcnt and lgkmcnt left at their maxima), for s_waitcnt.
+constexpr int vmcnt_only(int N) { return 0x0f70 | (N & 15) | ((N >> 4) << 14); }
+
+// Multi-stage form of gemm_split_dma_kernel: NS (3 or 4) LDS buffers.  While
+// tile kt is multiplied, the loads of tiles kt + 1 ... kt + NS - 1 are in
+// flight, so a tile's load has NS - 1 tiles of MFMA work to arrive in, where
+// the two-buffer kernel gives it one.  A workgroup barrier made by
+// __syncthreads() also waits for every outstanding load (vmcnt(0)), which
+// would cap the depth at one tile, so each wave instead waits only for its
+// own loads of tile kt (vmcnt = the loads of the NS - 2 later tiles, counted
+// at compile time) and then meets the others at a bare s_barrier.  The loads
+// of the tile issued at step kt go to the buffer read at step kt - 1, which
+// every wave has left by the time it passes step kt's barrier.  Past the last
+// tile the loads repeat tile 0 into buffers that are never read, so that the
+// count of loads in flight is the same at every step.  Same operand layout,
+// loads and per-16-wide-K product order as gemm_split_dma_kernel:
+// bit-identical results.  Needs ld <= kSplitDmaMaxLd.
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int NS>
+__global__ __launch_bounds__(WM *WN * 64) void gemm_split_ms_kernel(SplitGemmLaunch g) {
+    static_assert(NS == 3 || NS == 4, "stages");
+    typedef SplitTraits<T> Tr;
+    typedef typename Vec8<T>::type V8;
+    constexpr int NT = WM * WN * 64, NW = NT / 64;
+    constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
+    constexpr int CPR = SBK / 8;   // 16-byte chunks per tile row
+    constexpr int RPS = 64 / CPR;  // tile rows per 1 KB load
+    constexpr int A_PER = BM / RPS / NW, B_PER = BN / RPS / NW;  // loads per wave and part
+    static_assert(A_PER * NW * RPS == BM && B_PER * NW * RPS == BN && A_PER > 0 && B_PER > 0,
+                  "loads");
+    constexpr int LPT = NP * (A_PER + B_PER);  // loads per lane and tile
+    static_assert((NS - 2) * LPT <= 63, "vmcnt range");
+    constexpr int AS = BM * SBK, BS = BN * SBK, SS = NP * (AS + BS);
+    // one array per stage (the parts of X, then those of Y): the compiler
+    // tracks which LDS array each load writes, for only a few arrays, and
+    // then sees that the loads into one stage do not alias the operand reads
+    // from another
+    __shared__ __attribute__((aligned(16))) T S0[SS];
+    __shared__ __attribute__((aligned(16))) T S1[SS];
+    __shared__ __attribute__((aligned(16))) T S2[SS];
+    __shared__ __attribute__((aligned(16))) T S3[NS > 3 ? SS : 8];
+    __shared__ double red[NW];
+
+    const int n = g.n, ld = g.ld;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN, grp = lane >> 5, l32 = lane & 31;
+    int tm, tn;
+    tile_of_block(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    auto swz = [](int row) { return (row / (16 / CPR)) % CPR; };
+    const unsigned bytes = (unsigned)ld * (unsigned)ld * 2u;
+    auto rsrc = [&](const void *p) {
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        u4 r;
+        r[0] = (unsigned)a;
+        r[1] = (unsigned)(a >> 32) & 0xffffu;  // stride 0
+        r[2] = bytes;
+        r[3] = 0x00020000u;
+        return r;
+    };
+    u4 rx[NP], ry[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        rx[k] = rsrc(g.x[k]);
+        ry[k] = rsrc(g.y[k]);
+    }
+    unsigned a_off[A_PER], b_off[B_PER];
+#pragma unroll
+    for (int r = 0; r < A_PER; ++r) {
+        const int row = RPS * (wave + r * NW) + lane / CPR;
+        a_off[r] = (unsigned)(((m0 + row) * ld + 8 * ((lane % CPR) ^ swz(row))) * 2);
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER; ++r) {
+        const int row = RPS * (wave + r * NW) + lane / CPR;
+        b_off[r] = (unsigned)(((n0 + row) * ld + 8 * ((lane % CPR) ^ swz(row))) * 2);
+    }
+    auto load_tile = [&](int k0, T *st) {
+        const unsigned so = (unsigned)(k0 * 2);
+        const unsigned base = (unsigned)(uintptr_t)(__attribute__((address_space(3))) T *)st;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+#pragma unroll
+            for (int r = 0; r < A_PER; ++r)
+                lds_load16_asm(rx[k], base + 2u * (unsigned)(k * AS + (wave + r * NW) * 512), a_off[r],
+                               so);
+#pragma unroll
+            for (int r = 0; r < B_PER; ++r)
+                lds_load16_asm(ry[k],
+                               base + 2u * (unsigned)(NP * AS + k * BS + (wave + r * NW) * 512),
+                               b_off[r], so);
+        }
+    };
+
+    v16f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 256).
+    const int nk = (n + SBK - 1) / SBK;
+    auto body = [&](int kt, const T *st, T *nx) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_only((NS - 2) * LPT));  // this lane's loads of tile kt
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        const int kl = kt + NS - 1;
+        load_tile(kl < nk ? kl * SBK : 0, nx);
+#pragma unroll
+        for (int s = 0; s < SBK / 16; ++s) {
+            V8 a[NP][FM], b[NP][FN];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int row = wm * TM + i * 32 + l32;
+                    a[k][i] = *(const V8 *)(st + k * AS + row * SBK + 8 * ((2 * s + grp) ^ swz(row)));
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int row = wn * TN + j * 32 + l32;
+                    b[k][j] = *(const V8 *)(st + NP * AS + k * BS + row * SBK + 8 * ((2 * s + grp) ^ swz(row)));
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < NP; ++d)
+#pragma unroll
+                for (int u = 0; u <= d; ++u)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = mfma16<T>(a[u][i], b[d - u][j], acc[i][j]);
+        }
+    };
+    load_tile(0, S0);
+    load_tile(1 < nk ? SBK : 0, S1);
+    if constexpr (NS > 3) load_tile(2 < nk ? 2 * SBK : 0, S2);
+    for (int kt = 0; kt < nk; kt += NS) {
+        if constexpr (NS > 3) {
+            body(kt, S0, S3);
+            if (kt + 1 < nk) body(kt + 1, S1, S0);
+            if (kt + 2 < nk) body(kt + 2, S2, S1);
+            if (kt + 3 < nk) body(kt + 3, S3, S2);
+        } else {
+            body(kt, S0, S2);
+            if (kt + 1 < nk) body(kt + 1, S1, S0);
+            if (kt + 2 < nk) body(kt + 2, S2, S1);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(vmcnt_only(0));  // no LDS write still in flight at exit
+
+    // C = acc * 2^-2k, an exact power of two.
+    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
+    double ss = 0.0;
+    float *__restrict__ C = g.C;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
+                const int col = n0 + wn * TN + j * 32 + l32;
+                const float v = acc[i][j][r] * outScale;
+                if (row < n && col < n) {
+                    C[(int64_t)row * n + col] = v;
+                    ss += (double)v * (double)v;
+                }
+            }
+    ss = wave_sum_lane0(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w];
+        g.partC[blockIdx.x] = t;
+    }
+}
+
 // Largest ld whose ld x ld 16-bit part a 32-bit buffer offset covers
 // (a multiple of 256 with ld^2 * 2 < 2^31).
 constexpr int kSplitDmaMaxLd = 32512;
 
-// The LDS-DMA kernel when the padded parts fit a buffer's range, else the
-// register-staged one of the same tile (same results either way).
+// The LDS-DMA kernel when the padded parts fit a buffer's range (two LDS
+// buffers for DNS = 2, gemm_split_ms_kernel with DNS stages otherwise), else
+// the register-staged one of the same tile (same results in every case).
 template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int DWM, int DWN,
-          int DSBK>
+          int DSBK, int DNS>
 hipError_t launch_split_product(const SplitGemmLaunch &g, hipStream_t s) {
     if (g.ld > kSplitDmaMaxLd) return launch_gemm_split<T, NP, BM, BN, WM, WN, SBK>(g, s);
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_split_dma_kernel<T, NP, BM, BN, DWM, DWN, DSBK>), dim3(tiles),
-                       dim3(DWM * DWN * 64), 0, s, g);
+    if constexpr (DNS == 2)
+        hipLaunchKernelGGL((gemm_split_dma_kernel<T, NP, BM, BN, DWM, DWN, DSBK>), dim3(tiles),
+                           dim3(DWM * DWN * 64), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_split_ms_kernel<T, NP, BM, BN, DWM, DWN, DSBK, DNS>), dim3(tiles),
+                           dim3(DWM * DWN * 64), 0, s, g);
     return hipGetLastError();
 }
 
@@ -512,13 +720,13 @@ hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
 // 256 x 256 or 128 x 128 tiles, whichever has the higher estimated rate for
 // how its tile count fills the CUs (tile_fill_rate), with full-wave rates
 // measured on MI355X (16-bit MFMA TFLOP/s, LDS-DMA kernels): X3 modes
-// 256 x 256 1160, 128 x 128 1009; BF16X6 1228 and 1137.  Both accumulate every
-// output in the same order (per 16-wide K chunk, the fixed product order
-// above), so the two give bit-identical results.
+// 256 x 256 1160, 128 x 128 1009; BF16X6 (three-stage kernels) 1270 and
+// 1110.  Both accumulate every output in the same order (per 16-wide K chunk,
+// the fixed product order above), so the two give bit-identical results.
 int gemm_split_pick(int mode, int n) {
     const bool x6 = mode == MPOW_BF16X6;
-    const bool big = tile_fill_rate(x6 ? 1228.0 : 1160.0, n, 256, 256) >
-                     tile_fill_rate(x6 ? 1137.0 : 1009.0, n, 128, 128);
+    const bool big = tile_fill_rate(x6 ? 1270.0 : 1160.0, n, 256, 256) >
+                     tile_fill_rate(x6 ? 1110.0 : 1009.0, n, 128, 128);
     if (mode == MPOW_FP16X3) return big ? MPOW_KERNEL_GEMM_F16X3_256 : MPOW_KERNEL_GEMM_F16X3_128;
     if (x6) return big ? MPOW_KERNEL_GEMM_BF16X6_256 : MPOW_KERNEL_GEMM_BF16X6_128;
     return big ? MPOW_KERNEL_GEMM_BF16X3_256 : MPOW_KERNEL_GEMM_BF16X3_128;
@@ -555,27 +763,28 @@ const char *gemm_split_name(int kernel) {
         case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_dma_kernel<__bf16,2,128,128,2,4,64>";
         case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_dma_kernel<_Float16,2,256,256,2,4,32>";
         case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_dma_kernel<__bf16,2,256,256,2,4,32>";
-        case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_dma_kernel<__bf16,3,128,128,2,4,32>";
-        case MPOW_KERNEL_GEMM_BF16X6_256: return "gemm_split_dma_kernel<__bf16,3,256,256,2,4,16>";
+        case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_ms_kernel<__bf16,3,128,128,2,4,32,3>";
+        case MPOW_KERNEL_GEMM_BF16X6_256: return "gemm_split_ms_kernel<__bf16,3,256,256,2,4,16,3>";
         default: return nullptr;
     }
 }
 
 hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s) {
-    // register-staged tile <BM, BN, WM, WN, SBK>, then the LDS-DMA waves and K tile
+    // register-staged tile <BM, BN, WM, WN, SBK>, then the LDS-DMA waves, K tile
+    // and stages
     switch (kernel) {
         case MPOW_KERNEL_GEMM_F16X3_128:
-            return launch_split_product<_Float16, 2, 128, 128, 2, 2, 32, 2, 4, 64>(g, s);
+            return launch_split_product<_Float16, 2, 128, 128, 2, 2, 32, 2, 4, 64, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X3_128:
-            return launch_split_product<__bf16, 2, 128, 128, 2, 2, 32, 2, 4, 64>(g, s);
+            return launch_split_product<__bf16, 2, 128, 128, 2, 2, 32, 2, 4, 64, 2>(g, s);
         case MPOW_KERNEL_GEMM_F16X3_256:
-            return launch_split_product<_Float16, 2, 256, 256, 2, 4, 16, 2, 4, 32>(g, s);
+            return launch_split_product<_Float16, 2, 256, 256, 2, 4, 16, 2, 4, 32, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X3_256:
-            return launch_split_product<__bf16, 2, 256, 256, 2, 4, 16, 2, 4, 32>(g, s);
+            return launch_split_product<__bf16, 2, 256, 256, 2, 4, 16, 2, 4, 32, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X6_128:
-            return launch_split_product<__bf16, 3, 128, 128, 2, 2, 32, 2, 4, 32>(g, s);
+            return launch_split_product<__bf16, 3, 128, 128, 2, 2, 32, 2, 4, 32, 3>(g, s);
         case MPOW_KERNEL_GEMM_BF16X6_256:
-            return launch_split_product<__bf16, 3, 256, 256, 2, 4, 16, 2, 4, 16>(g, s);
+            return launch_split_product<__bf16, 3, 256, 256, 2, 4, 16, 2, 4, 16, 3>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
