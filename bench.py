@@ -828,8 +828,7 @@ def main():
         ms = float(np.median([ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]))
         per_case.append({"n": n, "p": p, "gemms": gemm_count(p), "ms": round(ms, 4),
                          "gflops": round(gemm_count(p) * 2.0 * n ** 3 / ms / 1e6, 1)})
-        if n <= 2048:
-            kept[(n, p)] = (outs[n].cpu().numpy(), float(scales[i].item()))
+        kept[(n, p)] = (outs[n].cpu().numpy(), float(scales[i].item()))
 
     mpow.mpow_plan_timing_reset(plan)
     # an event between consecutive steps (recorded on the stream, no host
@@ -888,7 +887,8 @@ def main():
             e = errs.get((c["n"], c["p"]))
             c["rel_err"] = float(f"{e[0]:.3e}") if e else None
             c["tol"] = float(f"{e[1]:.3e}") if e else None
-        result["errors_checked"] = f"{len(errs)} of {len(per_case)} cases (oracle leg's time budget)"
+        result["errors_checked"] = f"{len(errs)} of {len(per_case)} cases" + (
+            "" if len(errs) == len(per_case) else " (the rest past the oracle leg's time budget)")
         result["errors_within_tol"] = all(e[0] <= e[1] for e in errs.values())
     print(json.dumps(result), flush=True)
     return 0
