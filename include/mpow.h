@@ -89,7 +89,10 @@ int mpow_mode_for_tolerance(double tol, double floor, int wide_range);
 
 /* Plan flags. */
 #define MPOW_FLAG_TIMING 1u /* record a pair of HIP events around every product
-                               kernel launch; read with mpow_plan_timing */
+                               kernel launch; read with mpow_plan_timing.  The
+                               two records add about 7 us per launch on
+                               MI355X, as much as a whole product at n = 512:
+                               leave it off where small-matrix latency counts */
 #define MPOW_FLAG_POISON 2u /* testing: fill the workspace with NaN bytes at
                                creation instead of zeros, so a read of memory
                                the run has not written shows in the result */
