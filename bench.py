@@ -47,7 +47,8 @@ def measured_traffic():
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
         for key, name in (("kernel_source_sha256", "gemm_f32.hip"), ("tile_source_sha256", "gemm_f32_tile.h"),
-                          ("dma_tile_source_sha256", "gemm_f32_dma.h")):
+                          ("dma_tile_source_sha256", "gemm_f32_dma.h"),
+                          ("tile_order_source_sha256", "scale_device.h")):
             sha = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
             if kv.get(key) != sha:
                 return None

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_f32_dma_kernel(GemmLaunch g)
 
     const int n = g.n;
     int tm, tn;
-    tile_of_block(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
+    tile_of_block<(BM > BN ? 4 : 8)>(blockIdx.x, (n + BM - 1) / BM, (n + BN - 1) / BN, &tm, &tn);
     auto exps = [&]() { return operand_exponents<NT>(g, red); };
     const double ss = f32_tile_dma<BM, BN, WM, WN, BK, AXPI>(g.X, g.Y, exps, g.C, n, tm * BM,
                                                              tn * BN, As0, As1, Bs0, Bs1, red,

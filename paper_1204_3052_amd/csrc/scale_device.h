@@ -69,10 +69,14 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
 // each XCD has its own L2.  The block index is first permuted so that every
 // XCD gets one contiguous range of tiles, and that range is walked in bands
 // of GROUP_M tile rows, column by column, so that the workgroups an XCD runs
-// at the same time share rows of X and columns of Y in its L2.  A bijection
-// of [0, tilesM * tilesN).
+// at the same time share rows of X and columns of Y in its L2.  With 32 CUs
+// per XCD, the 32 concurrent tiles form a GROUP_M x (32 / GROUP_M) block,
+// which reads GROUP_M row panels of X and 32 / GROUP_M column panels of Y:
+// 8 suits square tiles, 4 tiles twice as tall as wide.  A bijection of
+// [0, tilesM * tilesN).
+template <int GROUP_M = 8>
 __device__ __forceinline__ void tile_of_block(int b, int tilesM, int tilesN, int *tm, int *tn) {
-    constexpr int XCDS = 8, GROUP_M = 8;
+    constexpr int XCDS = 8;
     const int T = tilesM * tilesN;
     int t = b;
     if (T >= 4 * XCDS) {
