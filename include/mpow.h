@@ -289,8 +289,8 @@ enum {
     MPOW_KERNEL_GEMM_F32_128_K2 = 12, /* float32 product, 128x128 tiles, 2x2 waves, K split in 2 */
     MPOW_KERNEL_GEMM_BF16X6_128 = 13, /* BF16 three-part six-product, 128x128 tiles */
     MPOW_KERNEL_GEMM_BF16X6_256 = 14, /* BF16 three-part six-product, 256x256 tiles, 8 waves */
-    MPOW_KERNEL_GEMM_F32_64_DMA = 15,  /* float32 product, 64x64 tiles, LDS-DMA loads, K tile 64 */
-    MPOW_KERNEL_GEMM_F32_128_DMA = 16, /* float32 product, 128x128 tiles, 2x4 waves, LDS-DMA, K tile 64 */
+    MPOW_KERNEL_GEMM_F32_64_DMA = 15,  /* float32 product, 64x64 tiles, LDS-DMA loads, K tile 32 */
+    MPOW_KERNEL_GEMM_F32_128_DMA = 16, /* float32 product, 128x128 tiles, 4x2 waves, LDS-DMA, K tile 32 */
     MPOW_KERNEL_GEMM_F32_256x128_DMA = 17, /* float32 product, 256x128 tiles, 4x2 waves, LDS-DMA */
     MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18, /* float32 product, 32x32 tiles, K split over 4 waves, whole K in LDS (n <= 512) */
     MPOW_KERNEL_COUNT = 19

@@ -120,8 +120,8 @@ constexpr Variant kVariants[] = {
     {MPOW_KERNEL_GEMM_F32_32_K8, 32, 32, 1, 1, 8, "gemm_f32_kernel<32,32,1,1,K8>"},
     {MPOW_KERNEL_GEMM_F32_64_K2, 64, 64, 2, 2, 2, "gemm_f32_kernel<64,64,2,2,K2>"},
     {MPOW_KERNEL_GEMM_F32_128_K2, 128, 128, 2, 2, 2, "gemm_f32_kernel<128,128,2,2,K2>"},
-    {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 2, 2, 1, "gemm_f32_dma_kernel<64,64,2,2,K64>"},
-    {MPOW_KERNEL_GEMM_F32_128_DMA, 128, 128, 2, 4, 1, "gemm_f32_dma_kernel<128,128,2,4,K64>"},
+    {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 2, 2, 1, "gemm_f32_dma_kernel<64,64,2,2>"},
+    {MPOW_KERNEL_GEMM_F32_128_DMA, 128, 128, 4, 2, 1, "gemm_f32_dma_kernel<128,128,4,2>"},
     {MPOW_KERNEL_GEMM_F32_256x128_DMA, 256, 128, 4, 2, 1, "gemm_f32_dma_kernel<256,128,4,2>"},
     {MPOW_KERNEL_GEMM_F32_32_K4_DMA, 32, 32, 1, 1, 4, "gemm_f32_dma_k4_kernel"},
 };
@@ -182,7 +182,7 @@ int gemm_pick(int n, bool vec4) {
             {MPOW_KERNEL_GEMM_F32_256x128_DMA, 256, 128, 151.0},
             {MPOW_KERNEL_GEMM_F32_256, 256, 256, 149.0},
             {MPOW_KERNEL_GEMM_F32_128_DMA, 128, 128, 147.0},
-            {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 132.0},
+            {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 141.0},
         };
         int best = MPOW_KERNEL_GEMM_F32_64_DMA;
         double best_rate = 0.0;
@@ -253,8 +253,8 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
                 hipLaunchKernelGGL((gemm_f32_kernel<256, 256, 2, 4, true, 1, false>),
                                    dim3(gemm_tiles(kernel, g.n)), dim3(512), 0, s, g);
             return hipGetLastError();
-        case MPOW_KERNEL_GEMM_F32_64_DMA: return launch_dma<64, 64, 2, 2, 64>(g, vec4, axpi, s);
-        case MPOW_KERNEL_GEMM_F32_128_DMA: return launch_dma<128, 128, 2, 4, 64>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_64_DMA: return launch_dma<64, 64, 2, 2, 32>(g, vec4, axpi, s);
+        case MPOW_KERNEL_GEMM_F32_128_DMA: return launch_dma<128, 128, 4, 2, 32>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_256x128_DMA:
             return launch_dma<256, 128, 4, 2, 32>(g, vec4, axpi, s);
         case MPOW_KERNEL_GEMM_F32_32_K4_DMA: {

@@ -20,8 +20,10 @@
 //    column halves.
 //  - Two LDS buffers (four separate arrays) alternate: the next K tile
 //    streams into one while the MFMAs read the other, one barrier per tile.
-//    BK = 64 halves the barriers of the smaller tiles; its tile is consumed
-//    as two 32-wide halves in order.
+//    BK = 64 (the batched kernel's 64 x 64 tile) halves the barriers and is
+//    consumed as two 32-wide halves in order; the single-matrix tiles use
+//    BK = 32, whose smaller LDS footprint lets more workgroups share a CU
+//    (measured faster for the 64 x 64 and 128 x 128 tiles from n = 1536 on).
 //  - v_mfma_f32_32x32x2_f32, each wave a (BM/WM) x (BN/WN) block of C, with
 //    the k-to-lane mapping and K order of f32_tile (K in steps of 32, lane
 //    half h taking k = 16h + 4q + t of each step), so every output element
