@@ -759,8 +759,8 @@ int gemm_split_tiles(int kernel, int n) {
 
 const char *gemm_split_name(int kernel) {
     switch (kernel) {
-        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_dma_kernel<_Float16,2,128,128,2,4,64>";
-        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_dma_kernel<__bf16,2,128,128,2,4,64>";
+        case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_dma_kernel<_Float16,2,128,128,4,2,64>";
+        case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_dma_kernel<__bf16,2,128,128,4,2,64>";
         case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_dma_kernel<_Float16,2,256,256,2,4,32>";
         case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_dma_kernel<__bf16,2,256,256,2,4,32>";
         case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_ms_kernel<__bf16,3,128,128,2,4,32,3>";
@@ -774,9 +774,9 @@ hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s
     // and stages
     switch (kernel) {
         case MPOW_KERNEL_GEMM_F16X3_128:
-            return launch_split_product<_Float16, 2, 128, 128, 2, 2, 32, 2, 4, 64, 2>(g, s);
+            return launch_split_product<_Float16, 2, 128, 128, 2, 2, 32, 4, 2, 64, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X3_128:
-            return launch_split_product<__bf16, 2, 128, 128, 2, 2, 32, 2, 4, 64, 2>(g, s);
+            return launch_split_product<__bf16, 2, 128, 128, 2, 2, 32, 4, 2, 64, 2>(g, s);
         case MPOW_KERNEL_GEMM_F16X3_256:
             return launch_split_product<_Float16, 2, 256, 256, 2, 4, 16, 2, 4, 32, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X3_256:
