@@ -826,6 +826,13 @@ def main():
     kept = {}
     reps = 5
     for i, (n, p) in enumerate(cases):
+        # run the case for at least 50 ms first: after a lighter case the
+        # clock takes that long to ramp back up
+        t_warm = time.perf_counter()
+        while time.perf_counter() - t_warm < 0.05:
+            mpow.mpow_run(plan_of[n], mats[n].data_ptr(), n, p, outs[n].data_ptr(),
+                          scales[i:i + 1].data_ptr(), stream.cuda_stream)
+            torch.cuda.synchronize(dev)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         ev[0].record(stream)
         for r in range(reps):
