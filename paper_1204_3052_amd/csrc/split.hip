@@ -720,13 +720,13 @@ hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
 // 256 x 256 or 128 x 128 tiles, whichever has the higher estimated rate for
 // how its tile count fills the CUs (tile_fill_rate), with full-wave rates
 // measured on MI355X (16-bit MFMA TFLOP/s, LDS-DMA kernels): X3 modes
-// 256 x 256 1160, 128 x 128 1009; BF16X6 (three-stage kernels) 1270 and
-// 1110.  Both accumulate every output in the same order (per 16-wide K chunk,
+// (4 x 2 waves) 256 x 256 1250, 128 x 128 1040; BF16X6 (three-stage
+// kernels) 1270 and 1110.  Both accumulate every output in the same order (per 16-wide K chunk,
 // the fixed product order above), so the two give bit-identical results.
 int gemm_split_pick(int mode, int n) {
     const bool x6 = mode == MPOW_BF16X6;
-    const bool big = tile_fill_rate(x6 ? 1270.0 : 1160.0, n, 256, 256) >
-                     tile_fill_rate(x6 ? 1110.0 : 1009.0, n, 128, 128);
+    const bool big = tile_fill_rate(x6 ? 1270.0 : 1250.0, n, 256, 256) >
+                     tile_fill_rate(x6 ? 1110.0 : 1040.0, n, 128, 128);
     if (mode == MPOW_FP16X3) return big ? MPOW_KERNEL_GEMM_F16X3_256 : MPOW_KERNEL_GEMM_F16X3_128;
     if (x6) return big ? MPOW_KERNEL_GEMM_BF16X6_256 : MPOW_KERNEL_GEMM_BF16X6_128;
     return big ? MPOW_KERNEL_GEMM_BF16X3_256 : MPOW_KERNEL_GEMM_BF16X3_128;
@@ -761,8 +761,8 @@ const char *gemm_split_name(int kernel) {
     switch (kernel) {
         case MPOW_KERNEL_GEMM_F16X3_128: return "gemm_split_dma_kernel<_Float16,2,128,128,4,2,64>";
         case MPOW_KERNEL_GEMM_BF16X3_128: return "gemm_split_dma_kernel<__bf16,2,128,128,4,2,64>";
-        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_dma_kernel<_Float16,2,256,256,2,4,32>";
-        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_dma_kernel<__bf16,2,256,256,2,4,32>";
+        case MPOW_KERNEL_GEMM_F16X3_256: return "gemm_split_dma_kernel<_Float16,2,256,256,4,2,32>";
+        case MPOW_KERNEL_GEMM_BF16X3_256: return "gemm_split_dma_kernel<__bf16,2,256,256,4,2,32>";
         case MPOW_KERNEL_GEMM_BF16X6_128: return "gemm_split_ms_kernel<__bf16,3,128,128,2,4,32,3>";
         case MPOW_KERNEL_GEMM_BF16X6_256: return "gemm_split_ms_kernel<__bf16,3,256,256,2,4,16,3>";
         default: return nullptr;
@@ -778,9 +778,9 @@ hipError_t gemm_split_launch(int kernel, const SplitGemmLaunch &g, hipStream_t s
         case MPOW_KERNEL_GEMM_BF16X3_128:
             return launch_split_product<__bf16, 2, 128, 128, 2, 2, 32, 4, 2, 64, 2>(g, s);
         case MPOW_KERNEL_GEMM_F16X3_256:
-            return launch_split_product<_Float16, 2, 256, 256, 2, 4, 16, 2, 4, 32, 2>(g, s);
+            return launch_split_product<_Float16, 2, 256, 256, 2, 4, 16, 4, 2, 32, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X3_256:
-            return launch_split_product<__bf16, 2, 256, 256, 2, 4, 16, 2, 4, 32, 2>(g, s);
+            return launch_split_product<__bf16, 2, 256, 256, 2, 4, 16, 4, 2, 32, 2>(g, s);
         case MPOW_KERNEL_GEMM_BF16X6_128:
             return launch_split_product<__bf16, 3, 128, 128, 2, 2, 32, 2, 4, 32, 3>(g, s);
         case MPOW_KERNEL_GEMM_BF16X6_256:
