@@ -124,7 +124,9 @@ def test_k_split_exact_cases(fplan, kernel):
 def test_split_mode_tile_sizes_bit_identical(mode, kernels):
     h = mpow.mpow_plan_create(0, 1100, 0, mode, 0)
     try:
-        for n in (100, 513, 1030):
+        # n = 17 and 40 give the multi-stage kernels fewer K tiles than (or
+        # as many as) they have LDS stages
+        for n in (17, 40, 100, 513, 1030):
             A = inputs.gaussian(n, 800 + n)
             for p in (3, 17):
                 (M0, s0), (M1, s1) = [forced(h, k, A, p) for k in kernels]
