@@ -82,8 +82,9 @@ constexpr int STS = 64;  // split tile edge
 // and the scaled floats to an LDS tile padded to 65 columns; it then reads 8
 // consecutive rows of one column (rows 8 (tid % 8) ..., columns tid/8 and
 // tid/8 + 32) and writes their transposed parts, again as 16-byte stores.
-// With the padding, the 64 lanes of a wave hit 64 distinct banks in both LDS
-// passes.  Every part is a function of the scaled entry alone, so both layouts
+// With the padding, the word addresses of a wave's 64 lanes fall in 64
+// distinct banks in both LDS passes (the compiler pairs two words per lane
+// into one access, which then takes two cycles).  Every part is a function of the scaled entry alone, so both layouts
 // hold the same values.
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
