@@ -718,16 +718,24 @@ hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s) {
     return hipGetLastError();
 }
 
-// 256 x 256 or 128 x 128 tiles, whichever has the higher estimated rate for
-// how its tile count fills the CUs (tile_fill_rate), with full-wave rates
-// measured on MI355X (16-bit MFMA TFLOP/s, LDS-DMA kernels): X3 modes
-// (4 x 2 waves) 256 x 256 1250, 128 x 128 1040; BF16X6 (three-stage
-// kernels) 1270 and 1110.  Both accumulate every output in the same order (per 16-wide K chunk,
-// the fixed product order above), so the two give bit-identical results.
+// 256 x 256 or 128 x 128 tiles, whichever has the higher estimated rate:
+// the rate for how its tile count fills the CUs (tile_fill_rate), with
+// full-wave rates measured on MI355X (16-bit MFMA TFLOP/s, LDS-DMA kernels):
+// X3 modes (4 x 2 waves) 256 x 256 1250, 128 x 128 1040; BF16X6 (three-stage
+// kernels) 1270 and 1110, times the useful fraction of the padded output
+// area, (n / (tiles per side x edge))^2, so that a small matrix (n <= 128:
+// one tile either way) takes the tile with less padding.  Both accumulate
+// every output in the same order (per 16-wide K chunk, the fixed product
+// order above), so the two give bit-identical results.
+static double split_rate(double full_wave, int n, int edge) {
+    const int t = (n + edge - 1) / edge;
+    const double useful = (double)n / (double)(t * edge);
+    return tile_fill_rate(full_wave, n, edge, edge) * useful * useful;
+}
+
 int gemm_split_pick(int mode, int n) {
     const bool x6 = mode == MPOW_BF16X6;
-    const bool big = tile_fill_rate(x6 ? 1270.0 : 1250.0, n, 256, 256) >
-                     tile_fill_rate(x6 ? 1110.0 : 1040.0, n, 128, 128);
+    const bool big = split_rate(x6 ? 1270.0 : 1250.0, n, 256) > split_rate(x6 ? 1110.0 : 1040.0, n, 128);
     if (mode == MPOW_FP16X3) return big ? MPOW_KERNEL_GEMM_F16X3_256 : MPOW_KERNEL_GEMM_F16X3_128;
     if (x6) return big ? MPOW_KERNEL_GEMM_BF16X6_256 : MPOW_KERNEL_GEMM_BF16X6_128;
     return big ? MPOW_KERNEL_GEMM_BF16X3_256 : MPOW_KERNEL_GEMM_BF16X3_128;

@@ -142,14 +142,14 @@ def embed(A, m):
 
 
 def test_split_tile_kernels_bit_identical(mplan):
-    # n = 1030 runs on 128 x 128 tiles and n = 2100 on 256 x 256 tiles; both
-    # add each output's products in the same order, and the extra K range of
-    # the embedding contributes exact zeros.
+    # n = 1030 runs on 128 x 128 tiles and n = 4096 on 256 x 256 tiles (the
+    # library's default picks); both add each output's products in the same
+    # order, and the extra K range of the embedding contributes exact zeros.
     mode, h = mplan
     A = inputs.gaussian(1030, 41)
     for p in (2, 17):
         M0, s0 = run_gpu(h, A, p)
-        M1, s1 = run_gpu(h, embed(A, 2100), p)
+        M1, s1 = run_gpu(h, embed(A, 4096), p)
         assert s0 == s1
         assert np.array_equal(M1[:1030, :1030], M0)
         assert not np.any(M1[1030:, :]) and not np.any(M1[:, 1030:])
