@@ -409,3 +409,145 @@ def test_floor_estimate_grows_with_p():
     assert 1e-9 < f2 < 1e-6
     assert f64 > f2
     assert O.floor_estimate(inputs.ones_matrix(8), 17, inputs.relative_signs(8, 1)) < 1e-6
+
+
+# ------------------------------------------- floor machinery: closed forms
+#
+# The floor term of every stated bar is the oracle's relative change under a
+# relative +-u input perturbation, u = 2^-24 the unit roundoff of float32
+# (half its machine epsilon).  These pins fix u, the perturbation, the power
+# and the error metric against values computed independently of the oracle:
+# exact rational arithmetic on diagonal matrices, and the first-order
+# perturbation series of A^p on dense ones.  A perturbation of 2^-23 or
+# 2^-22 (an epsilon in place of the unit roundoff) doubles or quadruples the
+# floor and fails each of them.
+
+from fractions import Fraction
+
+U32 = float(np.finfo(np.float32).eps) / 2.0  # float32 unit roundoff, 2^-24
+
+
+def _closed_form_diag_floor(signs, p):
+    """sqrt(mean_i ((1 + s_i u)^p - 1)^2) in exact rational arithmetic."""
+    u = Fraction(1, 2 ** 24)
+    terms = [((1 + int(s) * u) ** p - 1) ** 2 for s in np.ravel(signs)]
+    return math.sqrt(float(sum(terms) / len(terms)))
+
+
+def test_perturbation_is_float32_unit_roundoff():
+    rng = np.random.default_rng(3)
+    A = (rng.standard_normal((9, 9)) * 2.0 ** rng.integers(-40, 40, (9, 9))).astype(np.float32)
+    sg = inputs.relative_signs(9, 4)
+    P = O.perturbed(A, sg)
+    A64 = A.astype(np.float64)
+    rel = (P - A64) / A64
+    assert U32 == 2.0 ** -24
+    assert np.array_equal(rel, sg * U32)  # exact: entries are float32, u a power of two
+    assert np.array_equal(O.perturbed(np.zeros((3, 3)), inputs.relative_signs(3, 1)), np.zeros((3, 3)))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 17, 64, 256, 1023])
+def test_floor_estimate_scalar_identity_closed_form(p):
+    # D = c I_n with signs s: the perturbed power is c^p diag((1 + s_i u)^p),
+    # so the floor is the root mean square of (1 + s_i u)^p - 1, about p u.
+    n = 6
+    for c in (0.75, -1.5, 3.0):
+        D = (np.eye(n) * c).astype(np.float32)
+        sg = inputs.relative_signs(n, 10 + p)
+        got = O.floor_estimate(D, p, sg)
+        want = _closed_form_diag_floor(np.diag(sg), p)
+        assert abs(got - want) <= 1e-7 * want, (c, p, got, want)
+        # the same value with an epsilon of 2^-23 would be about twice as large
+        assert abs(got - 2 * want) > 0.4 * want
+
+
+@pytest.mark.parametrize("p", [1, 2, 5, 100, 1023])
+def test_floor_estimate_one_by_one(p):
+    for s in (-1.0, 1.0):
+        got = O.floor_estimate(np.array([[0.625]], dtype=np.float32), p, np.array([[s]]))
+        want = abs(float((1 + Fraction(int(s), 2 ** 24)) ** p - 1))
+        assert abs(got - want) <= 1e-7 * want, (p, s, got, want)
+
+
+@pytest.mark.parametrize("p", [2, 17, 256])
+def test_floor_estimate_rows_diagonal_closed_form(p):
+    # Row i of diag(d)^p only sees the perturbation of d_i: its relative
+    # change is |(1 + s_ii u)^p - 1|.
+    n = 8
+    d = np.array([0.5, -0.5, 0.5, 0.5, -0.5, 0.5, -0.5, 0.5], dtype=np.float32)
+    D = np.diag(d)
+    sg = inputs.relative_signs(n, 40 + p)
+    rows = [0, 3, 4, 7]
+    got = O.floor_estimate_rows(D, p, rows, sg)
+    for r, g in zip(rows, got):
+        want = abs(float((1 + Fraction(int(sg[r, r]), 2 ** 24)) ** p - 1))
+        assert abs(g - want) <= 1e-7 * want, (r, g, want)
+
+
+def test_row_rel_errs_closed_form():
+    # rows scaled by known factors (1 + delta_k) and carried with different
+    # power-of-two scales: the row errors are |delta_k| exactly up to rounding
+    rng = np.random.default_rng(8)
+    R_ref = rng.standard_normal((4, 16))
+    deltas = [3e-7, -1e-5, 0.0, 2.5e-3]
+    shifts = [0, 3, -7, 60]
+    R = np.stack([np.ldexp(R_ref[k] * (1 + deltas[k]), -shifts[k]) for k in range(4)])
+    errs = O.row_rel_errs(R, shifts, R_ref, [0] * 4)
+    for e, d in zip(errs, deltas):
+        assert abs(e - abs(d)) <= 1e-12 + 1e-9 * abs(d), (e, d)
+
+
+@pytest.mark.parametrize("p", [2, 17, 64])
+def test_floor_estimate_rows_match_full_power(p):
+    # The row method (p - 1 vector-matrix products) against the rows of the
+    # binary method's full power: two different computations of the same
+    # perturbed and unperturbed rows.
+    n = 24
+    A = inputs.gaussian(n, 50 + p)
+    sg = inputs.relative_signs(n, 60 + p)
+    rows = [0, 5, 11, 23]
+    got = O.floor_estimate_rows(A, p, rows, sg)
+    M, s = O.mpow_binary(A, p)
+    Mp, sp = O.mpow_binary(O.perturbed(A, sg), p)
+    V, Vp = O.to_value(M, s), O.to_value(Mp, sp)
+    for r, g in zip(rows, got):
+        want = float(np.linalg.norm(Vp[r] - V[r]) / np.linalg.norm(V[r]))
+        assert abs(g - want) <= 1e-5 * want, (r, g, want)
+
+
+@pytest.mark.parametrize("p", [2, 3, 17, 64])
+def test_floor_estimate_first_order_series(p):
+    # To first order in u, A^p moves by L = sum_{k=0}^{p-1} A^k E A^(p-1-k)
+    # with E = u (A o S) (o: entrywise product): the floor is ||L|| / ||A^p||
+    # up to terms of relative size about p u times the conditioning.  The
+    # recurrence L_{m+1} = L_m A + A^m E gives L without the oracle's code.
+    n = 12
+    A = inputs.gaussian(n, 70 + p).astype(np.float64)
+    sg = inputs.relative_signs(n, 80 + p)
+    E = A * sg * U32
+    P = np.eye(n)
+    L = np.zeros((n, n))
+    for _ in range(p):
+        L = L @ A + P @ E
+        P = P @ A
+    want = float(np.linalg.norm(L) / np.linalg.norm(P))
+    got = O.floor_estimate(A.astype(np.float32), p, sg)
+    assert abs(got - want) <= 1e-3 * want, (p, got, want)
+
+
+@pytest.mark.parametrize("eps", [2.0 ** -23, 2.0 ** -22, 2.0 ** -25])
+def test_floor_pins_catch_a_wrong_perturbation(monkeypatch, eps):
+    # Plant the slip in the oracle (an epsilon in place of the unit roundoff,
+    # or half of it) and check that the closed forms above reject it.
+    monkeypatch.setattr(O, "perturbed",
+                        lambda A, signs: np.asarray(A, dtype=np.float64) * (1.0 + signs * eps))
+    n, p = 6, 17
+    D = (np.eye(n) * 0.75).astype(np.float32)
+    sg = inputs.relative_signs(n, 10 + p)
+    want = _closed_form_diag_floor(np.diag(sg), p)
+    assert abs(O.floor_estimate(D, p, sg) - want) > 0.4 * want
+    d = np.diag(np.full(8, 0.5, dtype=np.float32))
+    sg8 = inputs.relative_signs(8, 42)
+    got = O.floor_estimate_rows(d, p, [0], sg8)[0]
+    want_row = abs(float((1 + Fraction(int(sg8[0, 0]), 2 ** 24)) ** p - 1))
+    assert abs(got - want_row) > 0.4 * want_row
