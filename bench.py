@@ -57,6 +57,11 @@ def measured_traffic():
         return None
 
 
+def host_cores() -> int:
+    """Cores this process may run on (its CPU affinity set)."""
+    return len(os.sched_getaffinity(0))
+
+
 def blas_threads() -> int:
     from threadpoolctl import threadpool_info
     return int(max((d.get("num_threads", 1) for d in threadpool_info()
@@ -90,7 +95,7 @@ def oracle_leg(cases, results, seconds_budget: float = 20.0):
             errs[(n, p)] = (err, tol_fp32(floor))
         if spent > seconds_budget:
             break
-    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "host_cores": host_cores(), "kind": "oracle",
            "sample": "FP64 oracle binary exponentiation (numpy matmul) on " + ", ".join(done)
                      + f"; {spent:.1f} s of oracle time"}
     return cpu, errs
@@ -116,7 +121,7 @@ def oracle_one_core(cases, seconds_budget: float = 5.0):
             done.append(f"N={n} p={p}")
             if spent > seconds_budget:
                 break
-    return {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+    return {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": 1, "host_cores": host_cores(), "kind": "oracle",
             "sample": "FP64 oracle binary exponentiation on one core on " + ", ".join(done)
                       + f"; {spent:.1f} s"}
 
@@ -207,7 +212,7 @@ def split_oracle_leg(A_np, kept, powers=(64, 1000)):
         for (name, q), (mode, M, s) in kept.items():
             if q == p:
                 errs[(name, p)] = (oracle.rel_err(M, s, *ref), tol_mode(mode, floor))
-    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "host_cores": host_cores(), "kind": "oracle",
            "sample": f"FP64 oracle binary exponentiation at N={n}, p in {tuple(powers)}; {spent:.1f} s"}
     return cpu, errs
 
@@ -458,7 +463,7 @@ def sample_oracle_leg(kept):
         tol = tol_mode(mode, oracle.floor_estimate(A, p, inputs.relative_signs(n, 3000 + i), ref=ref))
         errs.append({"n": n, "p": p, "mode": "bf16x3" if mode else "fp32", "rel_err": float(f"{err:.3e}"),
                      "tol": float(f"{tol:.3e}"), "within_tol": err <= tol})
-    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "host_cores": host_cores(), "kind": "oracle",
            "sample": f"FP64 oracle binary exponentiation on {len(kept)} sampled matrices; {spent:.1f} s"}
     return cpu, errs
 
@@ -606,7 +611,7 @@ def expm_oracle_leg(kept):
         Rp = oracle.expm(oracle.perturbed(A, inputs.relative_signs(n, 4000 + n)))
         floor = oracle.rel_err(Rp[0], Rp[1], *ref)
         errs[n] = (oracle.rel_err(M, s, *ref), tol_expm(floor, oracle.expm_squarings(A)))
-    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "kind": "oracle",
+    cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "host_cores": host_cores(), "kind": "oracle",
            "sample": f"FP64 oracle matrix exponential at N in {sorted(kept)}; {spent:.1f} s "
                      "(its own series runs to float64 resolution; rate counted as 7 + j products)"}
     return cpu, errs
@@ -736,6 +741,65 @@ def paper_workload(args):
                       "cpu_seq_note": "one FP64 three-loop product on one thread, times (p - 1)",
                       "rows": rows}), flush=True)
     return 0
+
+
+def stochastic_latency(dev, stream, reps: int = 200):
+    """Latency of one power on its own: the 128 x 128 row-stochastic matrix
+    (entries uniform, rows normalised to sum 1) raised to p = 64, one call
+    at a time with the device idle between calls.  Wall time covers the
+    host call and the wait for its completion; device time is between HIP
+    events recorded on the stream before and after the call.  Reported
+    beside the headline number, never in it."""
+    import numpy as np
+    import torch
+
+    from paper_1204_3052_amd import inputs, mpow
+
+    n, p = 128, 64
+    A_np = inputs.row_stochastic(n, 0)
+    A = torch.from_numpy(A_np).to(dev)
+    out = torch.empty_like(A)
+    sc = torch.zeros(1, dtype=torch.float64, device=dev)
+    h = mpow.mpow_plan_create(0, n, 0, mpow.MPOW_FP32, 0)
+    try:
+        def call():
+            mpow.mpow_run(h, A.data_ptr(), n, p, out.data_ptr(), sc.data_ptr(), stream.cuda_stream)
+
+        for _ in range(20):
+            call()
+        torch.cuda.synchronize(dev)
+        wall, devt = [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(reps):
+            t = time.perf_counter()
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize(dev)
+            wall.append((time.perf_counter() - t) * 1e3)
+            devt.append(e0.elapsed_time(e1))
+        M, s = out.cpu().numpy(), float(sc.item())
+    finally:
+        mpow.mpow_plan_destroy(h)
+    res = {"workload": "N=128 row-stochastic, p=64 (6 products), one call at a time",
+           "calls": reps,
+           "wall_ms": {"p50": round(float(np.percentile(wall, 50)), 4),
+                       "p99": round(float(np.percentile(wall, 99)), 4)},
+           "device_ms": {"p50": round(float(np.percentile(devt, 50)), 4),
+                         "p99": round(float(np.percentile(devt, 99)), 4)}}
+    return res, (A_np, p, M, s)
+
+
+def stochastic_oracle_check(res, kept):
+    """Oracle leg of the latency case: error and row-sum deviation."""
+    import numpy as np
+
+    import oracle
+    A_np, p, M, s = kept
+    ref = oracle.mpow_binary(A_np, p)
+    res["rel_err"] = float(f"{oracle.rel_err(M, s, *ref):.3e}")
+    res["tol"] = 1e-5
+    res["row_sum_dev"] = float(f"{np.max(np.abs(oracle.to_value(M, s).sum(axis=1) - 1.0)):.3e}")
 
 
 def main():
@@ -895,7 +959,10 @@ def main():
         "roofline": roofline,
         "per_case": per_case,
     }
+    lat, lat_kept = stochastic_latency(dev, stream)
+    result["latency_n128_p64"] = lat
     if not args.no_cpu_baseline:
+        stochastic_oracle_check(lat, lat_kept)
         cpu, errs = oracle_leg(cases, kept)
         result["cpu_baseline"] = cpu
         result["cpu_baseline_one_core"] = oracle_one_core(cases)

@@ -104,6 +104,11 @@ int mpow_mode_for_tolerance(double tol, double floor, int wide_range);
                                more max_n x max_n buffers (A^2, A^3, A^5, A^7).
                                Results then differ from the binary schedule's
                                in rounding (same tolerance). */
+#define MPOW_FLAG_SPLIT_PASS 16u /* BF16 modes: split each product's result into
+                               its BF16 parts in a separate pass (a float32
+                               write, a read and a launch per product) instead
+                               of in the product's epilogue; the same results
+                               bit for bit, for comparison and measurement */
 
 /* Upper bound on the number of products of one power (p < 2^63 needs <= 124). */
 #define MPOW_MAX_STEPS 126
@@ -293,7 +298,10 @@ enum {
     MPOW_KERNEL_GEMM_F32_128_DMA = 16, /* float32 product, 128x128 tiles, 4x2 waves, LDS-DMA, K tile 32 */
     MPOW_KERNEL_GEMM_F32_256x128_DMA = 17, /* float32 product, 256x128 tiles, 4x2 waves, LDS-DMA */
     MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18, /* float32 product, 32x32 tiles, K split over 4 waves, whole K in LDS (n <= 512) */
-    MPOW_KERNEL_COUNT = 19
+    MPOW_KERNEL_POWER_WG = 19, /* float32, n <= 128: the whole power in one launch of one
+                                  8-wave workgroup, base and running matrix resident in
+                                  LDS (mpow_run only; timing counts G(p) 2 n^3 per launch) */
+    MPOW_KERNEL_COUNT = 20
 };
 
 /* Timing of product launches recorded under MPOW_FLAG_TIMING since the last

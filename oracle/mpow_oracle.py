@@ -286,8 +286,10 @@ def floor_estimate(A: np.ndarray, p: int, signs: np.ndarray, ref=None) -> float:
     return rel_err(Mp, sp, M, s)
 
 
-def floor_estimate_rows(A: np.ndarray, p: int, rows, signs: np.ndarray) -> list:
-    R, s = mpow_rows(A, p, rows)
+def floor_estimate_rows(A: np.ndarray, p: int, rows, signs: np.ndarray, ref=None) -> list:
+    """Per-row floor_estimate of rows `rows` of A^p (the row method);
+    `ref` may pass the already computed (R, s) of those rows."""
+    R, s = mpow_rows(A, p, rows) if ref is None else ref
     Rp, sp = mpow_rows(perturbed(A, signs), p, rows)
     return row_rel_errs(Rp, sp, R, s)
 

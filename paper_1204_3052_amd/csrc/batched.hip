@@ -27,6 +27,7 @@
 #include "mpow_internal.h"
 #include "gemm_f32_dma.h"
 #include "gemm_f32_tile.h"
+#include "power_wg.h"
 
 namespace mpow {
 
@@ -330,6 +331,29 @@ __global__ __launch_bounds__(256) void batched_dma_kernel(BatchLaunch b) {
     run_jobs<256>(b, red, &claimed, product);
 }
 
+// Instance 4: every matrix's whole power in one 8-wave workgroup (power_wg.h):
+// LDS-resident for n <= 128, K panels streamed from the worker's scratch
+// (2 npad^2 floats) above.  One workgroup per CU (128 KB of LDS).
+__global__ __launch_bounds__(WG_NT, 1) void batched_wg_kernel(BatchLaunch b) {
+    __shared__ __attribute__((aligned(16))) float L0[WG_STAGE];
+    __shared__ __attribute__((aligned(16))) float L1[WG_STAGE];
+    __shared__ double red[WG_NT];
+    __shared__ int claimed;
+    BatchHeader *hdr = (BatchHeader *)b.desc;
+    const BatchItem *items = (const BatchItem *)(hdr + 1);
+    const int count = hdr->count;
+    float *scratch = b.scratch + (int64_t)blockIdx.x * 2 * b.slot_floats;
+    for (;;) {
+        if (threadIdx.x == 0) claimed = atomicAdd(&hdr->counter, 1);
+        __syncthreads();
+        const int it = claimed;
+        __syncthreads();
+        if (it >= count) break;
+        const BatchItem item = items[it];
+        wg_power<false>(item.A, item.n, item.p, item.out, item.scale, scratch, L0, L1, red);
+    }
+}
+
 }  // namespace
 
 // Default tile shape before tuning: the one that pads n least, larger on ties.
@@ -342,7 +366,9 @@ int batched_cfg_for(int n) {
 int batched_occupancy(int inst) {
     int blocks = 0;
     hipError_t e;
-    if (inst == 3)
+    if (inst == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_wg_kernel, WG_NT, 0);
+    else if (inst == 3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_dma_kernel, 256, 0);
     else if (inst == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<2>, 512, 0);
@@ -355,7 +381,9 @@ int batched_occupancy(int inst) {
 }
 
 hipError_t launch_batched(const BatchLaunch &b, int grid, int inst, hipStream_t s) {
-    if (inst == 3)
+    if (inst == 4)
+        hipLaunchKernelGGL(batched_wg_kernel, dim3(grid), dim3(WG_NT), 0, s, b);
+    else if (inst == 3)
         hipLaunchKernelGGL(batched_dma_kernel, dim3(grid), dim3(256), 0, s, b);
     else if (inst == 2)
         hipLaunchKernelGGL(batched_kernel<2>, dim3(grid), dim3(512), 0, s, b);

@@ -103,7 +103,8 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     if (!out_plan) return MPOW_ERR_INVALID;
     *out_plan = nullptr;
     if (max_n < 1 || max_batch < 0 || mode < 0 || mode > MPOW_BF16X6 ||
-        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON | MPOW_FLAG_EXPM | MPOW_FLAG_WINDOW)) != 0)
+        (flags & ~(MPOW_FLAG_TIMING | MPOW_FLAG_POISON | MPOW_FLAG_EXPM | MPOW_FLAG_WINDOW |
+                   MPOW_FLAG_SPLIT_PASS)) != 0)
         return MPOW_ERR_INVALID;
     if ((flags & MPOW_FLAG_WINDOW) && mode != MPOW_FP32) return MPOW_ERR_UNSUPPORTED;
     int ndev = 0;
@@ -161,6 +162,7 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
         return MPOW_ERR_DEVICE;
     }
     workspace_carve(plan->base, max_n, mode, &plan->ws);
+    plan->ws.split_pass = (flags & MPOW_FLAG_SPLIT_PASS) != 0;
     if (window) {
         char *q = plan->base + ws_bytes + b_bytes + e_bytes;
         for (int i = 0; i < 4; ++i) {
@@ -314,7 +316,7 @@ int mpow_fp32_kernel_for(int n, int aligned) {
 mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel) {
     if (!plan) return MPOW_ERR_INVALID;
     bool ok = kernel == -1;
-    if (!ok && plan->mode == MPOW_FP32) ok = gemm_is_f32(kernel);
+    if (!ok && plan->mode == MPOW_FP32) ok = gemm_is_f32(kernel) || kernel == MPOW_KERNEL_POWER_WG;
     if (!ok && plan->mode != MPOW_FP32) ok = gemm_split_mode(kernel) == plan->mode;
     if (!ok) return MPOW_ERR_INVALID;
     plan->ws.kernel = kernel;
@@ -331,7 +333,10 @@ mpow_status mpow_plan_timing(mpow_plan_t plan, int kernel, int64_t *launches, do
     if (launches) *launches = plan->timing.launches[kernel];
     if (total_ms) *total_ms = plan->timing.ms[kernel];
     if (total_flop) *total_flop = plan->timing.flop[kernel];
-    if (name) *name = gemm_name(kernel) ? gemm_name(kernel) : gemm_split_name(kernel);
+    if (name)
+        *name = kernel == MPOW_KERNEL_POWER_WG ? "power_wg_kernel"
+                : gemm_name(kernel)            ? gemm_name(kernel)
+                                               : gemm_split_name(kernel);
     return MPOW_SUCCESS;
 }
 

@@ -227,6 +227,9 @@ hipError_t launch_dma(const GemmLaunch &g, bool vec4, bool axpi, hipStream_t s) 
 int gemm_resolve(int kernel, int n, bool vec4) {
     const bool dma = vec4 && n <= DMA_MAX_N;
     switch (kernel) {
+        // the whole-power kernel is not a product kernel: where a product
+        // kernel is needed, the per-size default runs
+        case MPOW_KERNEL_POWER_WG: return gemm_pick(n, vec4);
         case MPOW_KERNEL_GEMM_F32_256: return vec4 ? kernel : MPOW_KERNEL_GEMM_F32_128;
         case MPOW_KERNEL_GEMM_F32_64_DMA: return dma ? kernel : MPOW_KERNEL_GEMM_F32_64;
         case MPOW_KERNEL_GEMM_F32_128_DMA:

@@ -30,6 +30,10 @@ struct Workspace {
     // [1] transposed, part k = 0 .. split_parts(mode) - 1
     void *sx[2][3] = {};
     void *sa[2][3] = {};
+    // BF16 modes (fused split): a second set of the running matrix's parts,
+    // so that a product writes the next operand's parts while it reads its own
+    void *sy[2][3] = {};
+    bool split_pass = false;  // BF16 modes: the separate split pass (MPOW_FLAG_SPLIT_PASS)
     int max_n = 0;
     int mode = MPOW_FP32;
     int kernel = -1;  // product kernel forced for every size, -1: per-size default
@@ -41,6 +45,23 @@ struct Workspace {
 };
 
 size_t round_up(size_t x, size_t a);
+
+// Pieces of the workspace layout (each 256-byte aligned): a running matrix,
+// its per-tile partial sums (the smallest product tile is 32 x 32), the
+// input's partial sums, and the per-product exponents.
+constexpr size_t ws_align(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t ws_buf_bytes(int max_n) { return ws_align((size_t)max_n * (size_t)max_n * 4); }
+constexpr size_t ws_part_bytes(int max_n) {
+    return ws_align(((size_t)max_n + 31) / 32 * (((size_t)max_n + 31) / 32) * 8);
+}
+constexpr int kMaxNormBlocks = 1024;  // partial sums of A (capacity of Workspace::partA)
+constexpr size_t ws_partA_bytes() { return ws_align((size_t)kMaxNormBlocks * 8); }
+constexpr size_t ws_escale_bytes() { return ws_align(((size_t)MPOW_NAIVE_MAX_P + 2) * 4); }
+// Bytes of a float32 workspace for matrices up to max_n.
+constexpr size_t fp32_workspace_bytes(int max_n) {
+    return 2 * ws_buf_bytes(max_n) + 2 * ws_part_bytes(max_n) + ws_partA_bytes() + ws_escale_bytes();
+}
+
 // Bytes of one workspace for matrices up to max_n in `mode` (256-aligned).
 size_t workspace_bytes(int max_n, int mode);
 // Lays a workspace out over [base, base + workspace_bytes(max_n, mode)).
@@ -100,6 +121,14 @@ hipError_t enqueue_expm(const Workspace &ws, float *T, const float *A, int n, in
 hipError_t enqueue_norm_exponent(const Workspace &ws, const float *A, int n, int *dev_e,
                                  hipStream_t s);
 int expm_squarings_for(int e);  // max(0, e + 2); 0 for INT_MIN
+// The whole power of one n x n matrix (n <= kPowerWgMaxN) in a single launch
+// of one workgroup that keeps its operands in LDS (power_wg.h).
+constexpr int kPowerWgMaxN = 128;
+hipError_t launch_power_wg(const float *A, int n, int64_t p, float *out, double *log2_scale,
+                           hipStream_t s);
+// mpow_run's float32 path takes launch_power_wg for n up to this size unless
+// a product kernel is forced.
+constexpr int kPowerWgAutoMaxN = 0;
 // The naive method: p - 1 chained float32 products X <- X.A (p <= MPOW_NAIVE_MAX_P).
 hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                                double *log2_scale, hipStream_t s, TimingSink *timing);
@@ -139,12 +168,26 @@ struct SplitLaunch {
 struct SplitGemmLaunch {
     const void *x[3];  // left operand's parts, row-major, ld
     const void *y[3];  // right operand's parts, transposed, ld
-    float *C;
+    float *C;          // float32 output (unused when the parts are written)
     double *partC;
     int n, ld;
+    // Fused split (BF16 modes): operands whose parts are those of an
+    // unnormalised matrix carry its partial sums of squares; the product is
+    // scaled by 2^-(eX + eY) in the epilogue (null: exponent 0).
+    const double *partX = nullptr;
+    int nPartX = 0;
+    const double *partY = nullptr;
+    int nPartY = 0;
+    int *eSlot = nullptr;    // block 0 records eX here (may be null)
+    // non-null: the epilogue writes C's parts, row-major (prm) and
+    // transposed (ptr), ld x ld, instead of C
+    void *prm[3] = {}, *ptr[3] = {};
 };
 
 int split_parts(int mode);  // 16-bit parts per operand (0 for MPOW_FP32)
+// BF16 modes: products write the next operand's parts in their epilogue
+// (no separate split pass after each product).
+inline bool split_fused(int mode) { return mode == MPOW_BF16X3 || mode == MPOW_BF16X6; }
 int gemm_split_mode(int kernel);  // the mode of a split kernel id, -1 if none
 int split_ld(int n);
 hipError_t launch_split(int mode, const SplitLaunch &sl, hipStream_t s);
@@ -174,7 +217,6 @@ const char *gemm_name(int kernel);
 hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s, bool axpi = false);
 
 // Scale and bookkeeping kernels.
-constexpr int kMaxNormBlocks = 1024;  // partial sums of A (capacity of Workspace::partA)
 int norm_blocks(int n);
 hipError_t launch_sumsq(const float *A, int n, double *part, int blocks, hipStream_t s);
 hipError_t launch_identity(float *out, int n, double *log2_scale, hipStream_t s);
@@ -206,8 +248,10 @@ struct BatchLaunch {
 };
 constexpr int kBatchMaxN = 256;
 constexpr int kTileBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
-constexpr int kBatchShapes = 3;   // tile shape ids of the batched kernel
-constexpr int kBatchInstances = 4;  // 0: 64x64; 1: 128x128 + 64x64; 2: 256x256; 3: LDS-DMA 128/64
+constexpr int kBatchShapes = 4;   // tile shape ids of the batched kernel (3: whole-power workgroup)
+// 0: 64x64; 1: 128x128 + 64x64; 2: 256x256; 3: LDS-DMA 128/64; 4: whole power
+// per 8-wave workgroup (power_wg.h)
+constexpr int kBatchInstances = 5;
 int batched_cfg_for(int n);
 // Resident workers per CU of kernel instance inst (0: 64x64 only, 1: 128x128
 // and 64x64, 2: 256x256 and 128x128 with 8 waves).

@@ -18,16 +18,16 @@ struct Layout {
 
 Layout layout_for(int max_n, int mode) {
     Layout z;
-    const size_t n = (size_t)max_n;
-    const size_t t32 = (n + 31) / 32;  // the smallest product tile is 32 x 32
-    z.buf = round_up(n * n * sizeof(float), 256);
-    z.part = round_up(t32 * t32 * sizeof(double), 256);
-    z.partA = round_up(kMaxNormBlocks * sizeof(double), 256);
-    z.escale = round_up((MPOW_NAIVE_MAX_P + 2) * sizeof(int), 256);
+    z.buf = ws_buf_bytes(max_n);
+    z.part = ws_part_bytes(max_n);
+    z.partA = ws_partA_bytes();
+    z.escale = ws_escale_bytes();
     const size_t ld = (size_t)split_ld(max_n);
     z.split = mode == MPOW_FP32 ? 0 : round_up(ld * ld * 2, 256);
-    // two operands (running matrix, A) x two layouts x the mode's parts
-    z.total = 2 * z.buf + 2 * z.part + z.partA + z.escale + 4 * split_parts(mode) * z.split;
+    // two operands (running matrix, A) x two layouts x the mode's parts, and
+    // for the fused split a second set of the running matrix's
+    const int sets = split_fused(mode) ? 6 : 4;
+    z.total = 2 * z.buf + 2 * z.part + z.partA + z.escale + sets * split_parts(mode) * z.split;
     return z;
 }
 
@@ -48,6 +48,10 @@ void workspace_carve(char *base, int max_n, int mode, Workspace *ws) {
         for (int k = 0; k < split_parts(mode); ++k) {
             ws->sx[l][k] = (void *)q; q += z.split;
             ws->sa[l][k] = (void *)q; q += z.split;
+            if (split_fused(mode)) {
+                ws->sy[l][k] = (void *)q;
+                q += z.split;
+            }
         }
     ws->max_n = max_n;
     ws->mode = mode;
@@ -240,8 +244,59 @@ hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const
     return launch_finish(X, n, partX, nPartX, ws.escale, p, out, log2_scale, s);
 }
 
-// Split-precision products: A is split once (both layouts); after every
-// product but the last, the float32 result is split again with its own scale.
+// Split-precision products: A is split once (both layouts).  FP16X3: after
+// every product but the last, the float32 result is split again with its own
+// scale (the FP16 parts need the scale before rounding).  BF16 modes: every
+// product but the last writes the parts of its unnormalised result itself
+// (BF16 keeps float32's exponent range, so rounding the unscaled value and
+// scaling afterwards by an exact power of two give the same parts), with its
+// partial sums; the next product derives the exponent from those and scales
+// its sums by 2^-(eX + eY) in its epilogue.
+hipError_t run_split_fused(const Workspace &ws, int n, const uint8_t *ops, int G, int kernel,
+                           float *out, double *log2_scale, hipStream_t s, TimingSink *timing,
+                           int64_t p) {
+    const int np = split_parts(ws.mode);
+    const int ld = split_ld(n);
+    const double flop = 2.0 * (double)n * (double)n * (double)n;
+    const int tiles = gemm_split_tiles(kernel, n);
+    void *const(*cur)[3] = ws.sa;  // the left operand's parts
+    const double *partX = nullptr;  // null: parts of a normalised matrix
+    int nPartX = 0;
+    for (int k = 1; k <= G; ++k) {
+        const bool sq = ops[k - 1] == 0;
+        SplitGemmLaunch g{};
+        for (int q = 0; q < np; ++q) {
+            g.x[q] = cur[0][q];
+            g.y[q] = sq ? cur[1][q] : ws.sa[1][q];
+        }
+        g.partX = partX;
+        g.nPartX = nPartX;
+        g.partY = sq ? partX : nullptr;
+        g.nPartY = sq ? nPartX : 0;
+        g.eSlot = k > 1 ? ws.escale + (k - 1) : nullptr;
+        g.partC = ws.part[k & 1];
+        g.n = n;
+        g.ld = ld;
+        void *const(*dest)[3] = cur == ws.sx ? ws.sy : ws.sx;
+        if (k < G) {
+            for (int q = 0; q < np; ++q) {
+                g.prm[q] = dest[0][q];
+                g.ptr[q] = dest[1][q];
+            }
+        } else {
+            g.C = ws.buf[G & 1];
+        }
+        TimingRecord rec{};
+        if (timing) MPOW_TRY(timing->start(kernel, flop, s, &rec));
+        MPOW_TRY(gemm_split_launch(kernel, g, s));
+        if (timing) MPOW_TRY(timing->stop(&rec, s));
+        cur = dest;
+        partX = g.partC;
+        nPartX = tiles;
+    }
+    return launch_finish(ws.buf[G & 1], n, ws.part[G & 1], tiles, ws.escale, p, out, log2_scale, s);
+}
+
 hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, const uint8_t *ops,
                      int G, int nbA, float *out, double *log2_scale, hipStream_t s,
                      TimingSink *timing) {
@@ -264,6 +319,8 @@ hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, cons
     }
     sl.eSlot = ws.escale;
     MPOW_TRY(launch_split(mode, sl, s));
+    if (split_fused(mode) && !ws.split_pass)
+        return run_split_fused(ws, n, ops, G, kernel, out, log2_scale, s, timing, p);
 
     for (int k = 1; k <= G; ++k) {
         void *const(*xs)[3] = (k == 1) ? ws.sa : ws.sx;
@@ -344,6 +401,17 @@ hipError_t run_fp32_window(const Workspace &ws, const float *A, int n, const uin
 hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                          double *log2_scale, hipStream_t s, TimingSink *timing) {
     if (p == 0) return launch_identity(out, n, log2_scale, s);
+    if (ws.mode == MPOW_FP32 && !ws.escaleY && n <= kPowerWgMaxN &&
+        (ws.kernel == MPOW_KERNEL_POWER_WG || (ws.kernel < 0 && n <= kPowerWgAutoMaxN))) {
+        // the whole power in one workgroup, operands resident in LDS
+        uint8_t ops[MPOW_MAX_STEPS];
+        const double flop = 2.0 * (double)n * (double)n * (double)n * schedule_of(p, ops);
+        TimingRecord rec{};
+        if (timing) MPOW_TRY(timing->start(MPOW_KERNEL_POWER_WG, flop, s, &rec));
+        MPOW_TRY(launch_power_wg(A, n, p, out, log2_scale, s));
+        if (timing) MPOW_TRY(timing->stop(&rec, s));
+        return hipSuccess;
+    }
     const int nbA = norm_blocks(n);
     MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
     uint8_t ops[MPOW_MAX_STEPS];
@@ -414,9 +482,13 @@ size_t batch_desc_bytes(int max_batch) {
     return sizeof(BatchHeader) + (size_t)max_batch * sizeof(BatchItem);
 }
 
-// Floats per per-worker scratch buffer: bmax^2 rounded up to 64 floats, so
-// every buffer starts 256-byte aligned (16-byte loads need 16).
-static int64_t batch_slot_floats(int bmax) { return (int64_t)round_up((size_t)bmax * bmax, 64); }
+// Floats per per-worker scratch buffer: the square of bmax rounded up to a
+// multiple of 32 (the whole-power instance pads its matrices so), rounded up
+// to 64 floats, so that every buffer starts 256-byte aligned.
+static int64_t batch_slot_floats(int bmax) {
+    const size_t np = ((size_t)bmax + 31) / 32 * 32;
+    return (int64_t)round_up(np * np, 64);
+}
 
 size_t batch_device_bytes(int max_batch, int bmax, int workers) {
     return 2 * round_up(batch_desc_bytes(max_batch), 256) +
@@ -472,6 +544,9 @@ hipError_t batch_wait_all(BatchContext *bc) {
 }
 
 int batch_instance(int need, bool all_vec) {
+    // need 3: a matrix of the batch takes the whole-power workgroup instance,
+    // which then runs every matrix of the batch
+    if (need == 3) return 4;
     // the LDS-DMA instance replaces the 128x128 + 64x64 one when every matrix
     // allows 16-byte loads
     return (need == 1 && all_vec) ? 3 : need;
@@ -511,7 +586,8 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         items[k].p = p[i];
         items[k].n = n[i];
         items[k].cfg = bc->cfg[(n[i] + 15) / 16];
-        const int nk = items[k].cfg == 2 ? 2 : (items[k].cfg == 0 ? 1 : 0);
+        const int c = items[k].cfg;
+        const int nk = c == 3 ? 3 : (c == 2 ? 2 : (c == 0 ? 1 : 0));
         need = nk > need ? nk : need;
         all_vec = all_vec && n[i] % 4 == 0 && ((uintptr_t)A[i] & 15) == 0;
     }

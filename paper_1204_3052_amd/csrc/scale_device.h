@@ -64,6 +64,17 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
     return v;
 }
 
+// Sum of `count` float64 partials by one wave, in a fixed order (lane l adds
+// partials l, l + 64, ... in turn, then the wave's fixed tree), returned to
+// every lane.  No barrier: each wave that calls it gets the same value.
+__device__ __forceinline__ double wave_sum_partials(const double *__restrict__ part, int count) {
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (int i = lane; i < count; i += 64) acc += part[i];
+    acc = wave_sum_lane0(acc);
+    return __shfl(acc, 0, 64);
+}
+
 // Tile order for a grid of tilesM x tilesN output tiles.  Workgroups are
 // dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8), and
 // each XCD has its own L2.  The block index is first permuted so that every

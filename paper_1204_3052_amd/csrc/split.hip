@@ -25,6 +25,8 @@
 // transposed (the right operand: row j holds column j, so a lane again reads
 // 8 consecutive k).  Both are zero-padded to ld = n rounded up to 256, so the
 // product kernel's loads need no bounds checks.
+#include <type_traits>
+
 #include "mpow_internal.h"
 #include "scale_device.h"
 
@@ -166,11 +168,100 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
 
 // ------------------------------------------------------------------ product
 
+// Operand exponents of a product whose operands' parts are those of
+// unnormalised matrices (the fused split): from the producers' partial sums,
+// reduced by each wave on its own (no barrier); 0 for an operand without
+// partial sums.  Block 0 records eX.
+struct SplitExps {
+    int x, y;
+};
+__device__ __forceinline__ SplitExps split_operand_exps(const SplitGemmLaunch &g) {
+    SplitExps e{0, 0};
+    if (g.partX) e.x = exponent_of_sumsq(wave_sum_partials(g.partX, g.nPartX));
+    if (g.partY) e.y = g.partY == g.partX ? e.x : exponent_of_sumsq(wave_sum_partials(g.partY, g.nPartY));
+    if (g.eSlot && blockIdx.x == 0 && threadIdx.x == 0) *g.eSlot = e.x;
+    return e;
+}
+
+// Epilogue of a split product tile: v = acc * 2^-2k (and * 2^-(eX + eY) for
+// the fused split, both exact powers of two); the tile's float64 sum of
+// squares of the valid v goes to partC[blockIdx.x].  The wave's block of
+// (32 FM) x (32 FN) values starts at (m0w, n0w).  Then either v is stored to
+// C, or (PARTS, g.prm and g.ptr set) v's NP 16-bit parts are, row-major and transposed,
+// for the next product: v = x0 + x1 (+ x2) as split_kernel forms them, on
+// the tile's whole area (its rows and columns past n hold zeros, which keeps
+// the zero padding the next product reads).  `red` holds NW doubles.
+template <typename T, int NP, int FM, int FN, int NW, bool PARTS>
+__device__ __forceinline__ void split_epilogue(const v16f (&acc)[FM][FN], const SplitGemmLaunch &g,
+                                               int m0w, int n0w, SplitExps ex, double *red) {
+    typedef SplitTraits<T> Tr;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = lane >> 5, l32 = lane & 31;
+    const int n = g.n, ld = g.ld;
+    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
+    const bool fused = ex.x + ex.y != 0;
+    const PowScale f = pow2_neg(ex.x + ex.y);
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int row0 = m0w + i * 32 + 8 * rb + 4 * grp;
+                const int col = n0w + j * 32 + l32;
+                float v[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    v[t] = acc[i][j][4 * rb + t] * outScale;
+                    if (fused) v[t] = v[t] * f.a * f.b;
+                    if (row0 + t < n && col < n) ss += (double)v[t] * (double)v[t];
+                }
+                if constexpr (PARTS) {
+                    T pv[NP][4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        float x = v[t];
+#pragma unroll
+                        for (int k = 0; k < NP; ++k) {
+                            const T h = (T)x;
+                            pv[k][t] = h;
+                            x = x - (float)h;  // exact: the rest after k + 1 parts
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        T *rm = (T *)g.prm[k];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) rm[(int64_t)(row0 + t) * ld + col] = pv[k][t];
+                        // four consecutive rows of column col: one 8-byte store
+                        typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+                        u16x4 w;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) w[t] = __builtin_bit_cast(unsigned short, pv[k][t]);
+                        *(u16x4 *)((T *)g.ptr[k] + (int64_t)col * ld + row0) = w;
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (row0 + t < n && col < n) g.C[(int64_t)(row0 + t) * n + col] = v[t];
+                }
+            }
+    ss = wave_sum_lane0(ss);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += red[w];
+        g.partC[blockIdx.x] = t;
+    }
+}
+
 // SBK is the K extent (16-bit elements) of one LDS tile; rows are padded by 8
 // elements so that 16-byte LDS reads are conflict-free.
-template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK>
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, bool PARTS>
 __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch g) {
-    typedef SplitTraits<T> Tr;
     typedef typename Vec8<T>::type V8;
     constexpr int SLD = SBK + 8;
     constexpr int NT = WM * WN * 64;
@@ -244,6 +335,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
     // m0 / n0 rows beyond n read the zero padding (ld is a multiple of 256).
     const int nk = (n + SBK - 1) / SBK;
     gload(0);
+    const SplitExps ex = split_operand_exps(g);
     sstore(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
@@ -277,40 +369,13 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_kernel(SplitGemmLaunch
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
-
-    // C = acc * 2^-2k, an exact power of two.
-    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
-    double ss = 0.0;
-    float *__restrict__ C = g.C;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
-                const int col = n0 + wn * TN + j * 32 + l32;
-                const float v = acc[i][j][r] * outScale;
-                if (row < n && col < n) {
-                    C[(int64_t)row * n + col] = v;
-                    ss += (double)v * (double)v;
-                }
-            }
-    ss = wave_sum_lane0(ss);
-    if (lane == 0) red[wave] = ss;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < WM * WN; ++w) t += red[w];
-        g.partC[blockIdx.x] = t;
-    }
+    split_epilogue<T, NP, FM, FN, WM * WN, PARTS>(acc, g, m0 + wm * TM, n0 + wn * TN, ex, red);
 }
 
-template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK>
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, bool PARTS>
 hipError_t launch_gemm_split(const SplitGemmLaunch &g, hipStream_t s) {
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_split_kernel<T, NP, BM, BN, WM, WN, SBK>), dim3(tiles),
+    hipLaunchKernelGGL((gemm_split_kernel<T, NP, BM, BN, WM, WN, SBK, PARTS>), dim3(tiles),
                        dim3(WM * WN * 64), 0, s, g);
     return hipGetLastError();
 }
@@ -326,9 +391,8 @@ hipError_t launch_gemm_split(const SplitGemmLaunch &g, hipStream_t s) {
 // fits LDS twice (double buffer), halving the barriers of the SBK = 16
 // register-staged tile.  Products per 16-wide K chunk in the same order as
 // gemm_split_kernel: bit-identical results.  Needs ld <= kSplitDmaMaxLd.
-template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK>
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, bool PARTS>
 __global__ __launch_bounds__(WM *WN * 64) void gemm_split_dma_kernel(SplitGemmLaunch g) {
-    typedef SplitTraits<T> Tr;
     typedef typename Vec8<T>::type V8;
     constexpr int NT = WM * WN * 64, NW = NT / 64;
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
@@ -437,40 +501,14 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_dma_kernel(SplitGemmLa
         __syncthreads();
     };
     load_tile(0, A0, B0);
+    const SplitExps ex = split_operand_exps(g);
     __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
     for (int kt = 0; kt < nk; kt += 2) {
         body(kt, A0, B0, A1, B1);
         if (kt + 1 < nk) body(kt + 1, A1, B1, A0, B0);
     }
-
-    // C = acc * 2^-2k, an exact power of two.
-    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
-    double ss = 0.0;
-    float *__restrict__ C = g.C;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
-                const int col = n0 + wn * TN + j * 32 + l32;
-                const float v = acc[i][j][r] * outScale;
-                if (row < n && col < n) {
-                    C[(int64_t)row * n + col] = v;
-                    ss += (double)v * (double)v;
-                }
-            }
-    ss = wave_sum_lane0(ss);
-    if (lane == 0) red[wave] = ss;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) t += red[w];
-        g.partC[blockIdx.x] = t;
-    }
+    split_epilogue<T, NP, FM, FN, NW, PARTS>(acc, g, m0 + wm * TM, n0 + wn * TN, ex, red);
 }
 
 // One 16-byte-per-lane buffer load into LDS (lane l's 16 bytes land at byte
@@ -511,10 +549,9 @@ constexpr int vmcnt_only(int N) { return 0x0f70 | (N & 15) | ((N >> 4) << 14); }
 // count of loads in flight is the same at every step.  Same operand layout,
 // loads and per-16-wide-K product order as gemm_split_dma_kernel:
 // bit-identical results.  Needs ld <= kSplitDmaMaxLd.
-template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int NS>
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int NS, bool PARTS>
 __global__ __launch_bounds__(WM *WN * 64) void gemm_split_ms_kernel(SplitGemmLaunch g) {
     static_assert(NS == 3 || NS == 4, "stages");
-    typedef SplitTraits<T> Tr;
     typedef typename Vec8<T>::type V8;
     constexpr int NT = WM * WN * 64, NW = NT / 64;
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
@@ -633,6 +670,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_ms_kernel(SplitGemmLau
     load_tile(0, S0);
     load_tile(1 < nk ? SBK : 0, S1);
     if constexpr (NS > 3) load_tile(2 < nk ? 2 * SBK : 0, S2);
+    const SplitExps ex = split_operand_exps(g);
     for (int kt = 0; kt < nk; kt += NS) {
         if constexpr (NS > 3) {
             body(kt, S0, S3);
@@ -646,34 +684,7 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_split_ms_kernel(SplitGemmLau
         }
     }
     __builtin_amdgcn_s_waitcnt(vmcnt_only(0));  // no LDS write still in flight at exit
-
-    // C = acc * 2^-2k, an exact power of two.
-    const float outScale = ldexpf(1.0f, -2 * Tr::kShift);
-    double ss = 0.0;
-    float *__restrict__ C = g.C;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * TM + i * 32 + 8 * (r >> 2) + 4 * grp + (r & 3);
-                const int col = n0 + wn * TN + j * 32 + l32;
-                const float v = acc[i][j][r] * outScale;
-                if (row < n && col < n) {
-                    C[(int64_t)row * n + col] = v;
-                    ss += (double)v * (double)v;
-                }
-            }
-    ss = wave_sum_lane0(ss);
-    if (lane == 0) red[wave] = ss;
-    __syncthreads();
-    if (tid == 0) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) t += red[w];
-        g.partC[blockIdx.x] = t;
-    }
+    split_epilogue<T, NP, FM, FN, NW, PARTS>(acc, g, m0 + wm * TM, n0 + wn * TN, ex, red);
 }
 
 // Largest ld whose ld x ld 16-bit part a 32-bit buffer offset covers
@@ -684,17 +695,31 @@ constexpr int kSplitDmaMaxLd = 32512;
 // buffers for DNS = 2, gemm_split_ms_kernel with DNS stages otherwise), else
 // the register-staged one of the same tile (same results in every case).
 template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int DWM, int DWN,
-          int DSBK, int DNS>
-hipError_t launch_split_product(const SplitGemmLaunch &g, hipStream_t s) {
-    if (g.ld > kSplitDmaMaxLd) return launch_gemm_split<T, NP, BM, BN, WM, WN, SBK>(g, s);
+          int DSBK, int DNS, bool PARTS>
+hipError_t launch_split_product_as(const SplitGemmLaunch &g, hipStream_t s) {
+    if (g.ld > kSplitDmaMaxLd) return launch_gemm_split<T, NP, BM, BN, WM, WN, SBK, PARTS>(g, s);
     const int tiles = ((g.n + BM - 1) / BM) * ((g.n + BN - 1) / BN);
     if constexpr (DNS == 2)
-        hipLaunchKernelGGL((gemm_split_dma_kernel<T, NP, BM, BN, DWM, DWN, DSBK>), dim3(tiles),
-                           dim3(DWM * DWN * 64), 0, s, g);
+        hipLaunchKernelGGL((gemm_split_dma_kernel<T, NP, BM, BN, DWM, DWN, DSBK, PARTS>),
+                           dim3(tiles), dim3(DWM * DWN * 64), 0, s, g);
     else
-        hipLaunchKernelGGL((gemm_split_ms_kernel<T, NP, BM, BN, DWM, DWN, DSBK, DNS>), dim3(tiles),
-                           dim3(DWM * DWN * 64), 0, s, g);
+        hipLaunchKernelGGL((gemm_split_ms_kernel<T, NP, BM, BN, DWM, DWN, DSBK, DNS, PARTS>),
+                           dim3(tiles), dim3(DWM * DWN * 64), 0, s, g);
     return hipGetLastError();
+}
+
+// The instance that writes the result's parts (the fused split; BF16 only)
+// when g.prm is set, else the one that writes the float32 result.
+template <typename T, int NP, int BM, int BN, int WM, int WN, int SBK, int DWM, int DWN,
+          int DSBK, int DNS>
+hipError_t launch_split_product(const SplitGemmLaunch &g, hipStream_t s) {
+    if constexpr (std::is_same<T, __bf16>::value) {
+        if (g.prm[0])
+            return launch_split_product_as<T, NP, BM, BN, WM, WN, SBK, DWM, DWN, DSBK, DNS, true>(g, s);
+    } else {
+        if (g.prm[0]) return hipErrorInvalidValue;  // FP16 parts need the scale first
+    }
+    return launch_split_product_as<T, NP, BM, BN, WM, WN, SBK, DWM, DWN, DSBK, DNS, false>(g, s);
 }
 
 }  // namespace

@@ -1,6 +1,5 @@
 // Device bodies of the memory-bound steps of a power (the input's sum of
-// squares and the final rescale), shared by their stand-alone kernels and by
-// the single-launch power kernel, so that both compute the same bits.
+// squares and the final rescale), used by their stand-alone kernels.
 #pragma once
 
 #include "scale_device.h"

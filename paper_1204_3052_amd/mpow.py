@@ -31,6 +31,7 @@ MPOW_FLAG_TIMING = 1
 MPOW_FLAG_POISON = 2
 MPOW_FLAG_EXPM = 4
 MPOW_FLAG_WINDOW = 8
+MPOW_FLAG_SPLIT_PASS = 16
 MPOW_TUNE_FORCE = 1
 TILE_TABLE_LEN = 17
 MPOW_MAX_STEPS = 126
@@ -55,7 +56,8 @@ MPOW_KERNEL_GEMM_F32_64_DMA = 15
 MPOW_KERNEL_GEMM_F32_128_DMA = 16
 MPOW_KERNEL_GEMM_F32_256x128_DMA = 17
 MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18
-MPOW_KERNEL_COUNT = 19
+MPOW_KERNEL_POWER_WG = 19
+MPOW_KERNEL_COUNT = 20
 
 # every symbol include/mpow.h declares
 EXPORTS = (
@@ -393,27 +395,137 @@ def _check_matrix(A):
         raise ValueError("A must be a contiguous square matrix")
 
 
-def run(A, p: int, plan: Plan | None = None, out=None, return_scale: bool = False, stream=None):
-    """A^p of a square float32 device tensor.
+def _stream_handle(device, stream):
+    import torch
+    st = torch.cuda.current_stream(device) if stream is None else stream
+    return st.cuda_stream
 
-    Returns `out` (A^p rounded to float32), or (M, s) with A^p = M * 2^s when
-    return_scale is true; s is a one-element float64 device tensor."""
+
+def run(A, p: int, plan: Plan | None = None, out=None, return_scale: bool = False, stream=None,
+        mode: int | None = None):
+    """A^p of a square float32 device tensor (mpow_run).
+
+    mode: the product arithmetic (MPOW_FP32, MPOW_FP16X3, MPOW_BF16X3,
+    MPOW_BF16X6); None takes the plan's, or MPOW_FP32 for a temporary plan.
+    A given plan must have been created for that mode.  Returns `out` (A^p
+    rounded to float32), or (M, s) with A^p = M * 2^s when return_scale is
+    true; s is a one-element float64 device tensor."""
     import torch
     _check_matrix(A)
     n = A.shape[0]
     own = plan is None
     if own:
-        plan = Plan(n, device=A.device.index)
+        plan = Plan(n, mode=MPOW_FP32 if mode is None else int(mode), device=A.device.index)
+    elif mode is not None and int(mode) != plan.mode:
+        raise ValueError(f"plan was created for mode {plan.mode}, not {mode}")
     try:
         if out is None:
             out = torch.empty_like(A)
         scale = torch.empty(1, dtype=torch.float64, device=A.device) if return_scale else None
-        st = torch.cuda.current_stream(A.device) if stream is None else stream
         mpow_run(plan.handle, A.data_ptr(), n, p, out.data_ptr(),
-                 scale.data_ptr() if scale is not None else None, st.cuda_stream)
+                 scale.data_ptr() if scale is not None else None, _stream_handle(A.device, stream))
         if own:
             torch.cuda.synchronize(A.device)
     finally:
         if own:
             plan.close()
     return (out, scale) if return_scale else out
+
+
+def run_batched(As, ps, plan: Plan | None = None, outs=None, return_scale: bool = False,
+                stream=None):
+    """Independent powers As[i]^ps[i] in one persistent launch (mpow_run_batched).
+
+    As: sequence of square float32 device tensors (n <= 256) on one device;
+    ps: powers.  Returns the list of outputs, or (outputs, s) with s a
+    float64 device tensor of one log2 scale per matrix when return_scale is
+    true.  A given plan must be a float32 plan with max_batch >= len(As) and
+    max_n >= the largest n."""
+    import torch
+    As = list(As)
+    ps = [int(p) for p in ps]
+    if len(ps) != len(As):
+        raise ValueError("As and ps differ in length")
+    for A in As:
+        _check_matrix(A)
+    count = len(As)
+    if count == 0:
+        return ([], None) if return_scale else []
+    dev = As[0].device
+    if any(A.device != dev for A in As):
+        raise ValueError("all matrices must be on one device")
+    ns = [A.shape[0] for A in As]
+    if outs is None:
+        outs = [torch.empty_like(A) for A in As]
+    own = plan is None
+    if own:
+        plan = Plan(max(ns), max_batch=count, device=dev.index)
+    try:
+        scale = torch.empty(count, dtype=torch.float64, device=dev) if return_scale else None
+        mpow_run_batched(plan.handle, count, [A.data_ptr() for A in As], ns, ps,
+                         [o.data_ptr() for o in outs],
+                         scale.data_ptr() if scale is not None else None, _stream_handle(dev, stream))
+        if own:
+            torch.cuda.synchronize(dev)
+    finally:
+        if own:
+            plan.close()
+    return (outs, scale) if return_scale else outs
+
+
+class Server:
+    """Request server over mpow_srv_* (continuous batching of independent powers).
+
+    submit() queues A^p and returns the request id; the server keeps the
+    request's tensors alive until poll() has returned its completion record.
+    Usable as a context manager; close() drains every request first."""
+
+    def __init__(self, max_n: int, hbm_budget: int, n_streams: int = 4, max_batch: int = 1024,
+                 device: int | None = None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.handle = mpow_srv_create(self.device, max_n, hbm_budget, n_streams, max_batch)
+        self._held = {}
+
+    def submit(self, A, p: int, mode: int = MPOW_FP32, out=None, return_scale: bool = False):
+        """Queues A^p.  Returns (id, out) or (id, out, s) with s a one-element
+        float64 device tensor; both are valid once the request has completed."""
+        import torch
+        _check_matrix(A)
+        if out is None:
+            out = torch.empty_like(A)
+        scale = torch.empty(1, dtype=torch.float64, device=A.device) if return_scale else None
+        rid = mpow_srv_submit(self.handle, A.data_ptr(), A.shape[0], int(p), int(mode), out.data_ptr(),
+                              scale.data_ptr() if scale is not None else None)
+        self._held[rid] = (A, out, scale)
+        return (rid, out, scale) if return_scale else (rid, out)
+
+    def poll(self, max_items: int = 4096) -> list:
+        done = mpow_srv_poll(self.handle, max_items)
+        for c in done:
+            self._held.pop(c["id"], None)
+        return done
+
+    def wait_idle(self, timeout_s: float = 60.0) -> None:
+        mpow_srv_wait_idle(self.handle, timeout_s)
+
+    def stats(self) -> dict:
+        return mpow_srv_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            mpow_srv_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

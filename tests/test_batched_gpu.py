@@ -255,10 +255,12 @@ def test_tile_shapes_bit_identical(plans):
     saved = mpow.mpow_plan_tile_table(hb)
     results = []
     # all 128x128, all 64x64 (the instance without the large tile), a mix of
-    # both in one launch, all 256x256 (the 8-wave instance), and a mix of all
+    # both in one launch, all 256x256 (the 8-wave instance), a mix of those,
+    # the whole-power workgroup instance, and a mix including it
     tables = [[0] * mpow.TILE_TABLE_LEN, [1] * mpow.TILE_TABLE_LEN,
               [b % 2 for b in range(mpow.TILE_TABLE_LEN)], [2] * mpow.TILE_TABLE_LEN,
-              [b % 3 for b in range(mpow.TILE_TABLE_LEN)]]
+              [b % 3 for b in range(mpow.TILE_TABLE_LEN)], [3] * mpow.TILE_TABLE_LEN,
+              [b % 4 for b in range(mpow.TILE_TABLE_LEN)]]
     for table in tables:
         mpow.mpow_plan_tile_table(hb, table)
         pk.out.fill_(float("nan"))
@@ -287,6 +289,31 @@ def test_autotune_and_cache(plans, tmp_path):
         assert mpow.mpow_plan_tile_table(h2)[1:] == table[1:]
     finally:
         mpow.mpow_plan_destroy(h2)
-    for bad in (3, 7, -1):
+    for bad in (4, 7, -1):
         with pytest.raises(mpow.MpowError):
             mpow.mpow_plan_tile_table(hb, [bad] * mpow.TILE_TABLE_LEN)
+
+
+def test_whole_power_instance_equals_plain_bitwise(plans):
+    # the whole-power workgroup instance (tile shape 3) on ragged sizes of
+    # any alignment, and on multiple-of-4 sizes with 2^+-70-scaled inputs
+    hb, hp = plans
+    saved = mpow.mpow_plan_tile_table(hb)
+    mpow.mpow_plan_tile_table(hb, [3] * mpow.TILE_TABLE_LEN)
+    try:
+        for mats, ps in (edge_batch(6), edge4_batch(7)):
+            pk = Packed(mats)
+            run_batch(hb, pk, ps)
+            for i, (A, p) in enumerate(zip(mats, ps)):
+                Mb, sb = pk.result(i)
+                Mp, sp = run_gpu(hp, A, p)
+                assert np.array_equal(Mb, Mp) and sb == sp, (A.shape[0], p)
+            pk.out.fill_(float("nan"))
+            run_batch(hb, pk, ps, log_scale=False)
+            for i, (A, p) in enumerate(zip(mats, ps)):
+                if i % 5 == 0:
+                    ob, _ = pk.result(i)
+                    op, _ = run_gpu(hp, A, p, log_scale=False)
+                    assert np.array_equal(ob, op), (A.shape[0], p)
+    finally:
+        mpow.mpow_plan_tile_table(hb, saved)

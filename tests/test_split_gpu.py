@@ -180,3 +180,39 @@ def test_mode_for_tolerance_end_to_end(n, p, tol, wide):
     err = oracle.rel_err(M, s, *ref)
     print(f"    tol={tol} floor={floor:.2e} mode={mode} err={err:.3e}")
     assert err <= tol
+
+
+BF16_KERNELS = {mpow.MPOW_BF16X3: (mpow.MPOW_KERNEL_GEMM_BF16X3_128, mpow.MPOW_KERNEL_GEMM_BF16X3_256),
+                mpow.MPOW_BF16X6: (mpow.MPOW_KERNEL_GEMM_BF16X6_128, mpow.MPOW_KERNEL_GEMM_BF16X6_256)}
+
+
+@pytest.mark.parametrize("mode", [mpow.MPOW_BF16X3, mpow.MPOW_BF16X6])
+def test_fused_split_equals_split_pass(mode):
+    # The BF16 products write the next operand's parts in their epilogue
+    # (parts of the unnormalised result, the exponent folded into the next
+    # product); the separate pass splits the normalised float32 result.  BF16
+    # rounding commutes with exact power-of-two scaling, so both give the same
+    # bits.  The fused plan's workspace starts NaN-filled: only what the
+    # products write may be read.
+    fused = mpow.mpow_plan_create(0, 1100, 0, mode, mpow.MPOW_FLAG_POISON)
+    ref = mpow.mpow_plan_create(0, 1100, 0, mode, mpow.MPOW_FLAG_SPLIT_PASS)
+    try:
+        for kernel in (-1,) + BF16_KERNELS[mode]:
+            mpow.mpow_plan_set_kernel(fused, kernel)
+            mpow.mpow_plan_set_kernel(ref, kernel)
+            for n in (1, 17, 100, 129, 300, 1030):
+                A = inputs.gaussian(n, 4000 + n)
+                for p in (2, 3, 17, 100):
+                    for log in (True, False):
+                        Mf, sf = run_gpu(fused, A, p, log_scale=log)
+                        Mr, sr = run_gpu(ref, A, p, log_scale=log)
+                        assert np.array_equal(Mf, Mr) and sf == sr, (kernel, n, p, log)
+            # an input scaled far from 1: the parts of the first product's
+            # result come from the exactly rescaled values
+            A = np.ldexp(inputs.gaussian(256, 9), 90).astype(np.float32)
+            Mf, sf = run_gpu(fused, A, 77)
+            Mr, sr = run_gpu(ref, A, 77)
+            assert np.array_equal(Mf, Mr) and sf == sr, kernel
+    finally:
+        mpow.mpow_plan_destroy(fused)
+        mpow.mpow_plan_destroy(ref)
