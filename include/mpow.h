@@ -194,6 +194,30 @@ mpow_status mpow_run(mpow_plan_t plan, const float *A, int n, int64_t p, float *
 mpow_status mpow_run_naive(mpow_plan_t plan, const float *A, int n, int64_t p, float *out,
                            double *log2_scale, void *stream);
 
+/* Largest n mpow_run_noalloc accepts. */
+#define MPOW_NOALLOC_MAX_N 2048
+
+/* mpow_run without a plan and without any device allocation, for callers
+ * that cannot allocate device memory: code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  It computes what
+ * mpow_run does on a float32 plan with default kernels (the same kernels,
+ * so the same bits), on the CURRENT device; `stream` must belong to it
+ * (NULL: the null stream).
+ * Workspace: a fixed device array of about 32 MiB (the float32 workspace
+ * of a 2048 x 2048 power) inside the library, one per GPU, held from the
+ * library's first use on that GPU until the process ends.  The first call
+ * on a device looks up that device's copy (no allocation); no call
+ * allocates or frees device or pinned memory.
+ * Concurrency: every call on one GPU shares that GPU's array, so two calls
+ * whose work overlaps on the device (different streams, not ordered by
+ * events) race and give undefined results; calls on one stream, or ordered
+ * by events, are safe.  Nothing in the array needs clearing between calls.
+ * Arguments as mpow_run (A, out, log2_scale device pointers, out may be A).
+ * Errors: INVALID (arguments, or a stream of another device), UNSUPPORTED
+ * (n > MPOW_NOALLOC_MAX_N; nothing enqueued), DEVICE (HIP failure). */
+mpow_status mpow_run_noalloc(const float *A, int n, int64_t p, float *out, double *log2_scale,
+                             void *stream);
+
 /* Matrix exponential e^A by scaling and squaring, float32 products (the
  * power's kernels; an extension beyond the paper, whose subject is A^p):
  * e^A = (e^B)^(2^j) with B = A * 2^-j exact; e^B is the degree-8 Taylor

@@ -36,6 +36,7 @@ MPOW_TUNE_FORCE = 1
 TILE_TABLE_LEN = 17
 MPOW_MAX_STEPS = 126
 MPOW_NAIVE_MAX_P = 4096
+MPOW_NOALLOC_MAX_N = 2048
 
 MPOW_KERNEL_GEMM_F32_128 = 0
 MPOW_KERNEL_GEMM_F32_64 = 1
@@ -62,7 +63,8 @@ MPOW_KERNEL_COUNT = 20
 # every symbol include/mpow.h declares
 EXPORTS = (
     "mpow_status_str", "mpow_gemm_count", "mpow_schedule", "mpow_window_schedule", "mpow_workspace_bytes",
-    "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_batched", "mpow_expm",
+    "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_noalloc",
+    "mpow_run_batched", "mpow_expm",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
     "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_fp32_kernel_for",
     "mpow_mode_for_tolerance",
@@ -135,6 +137,7 @@ def _load():
         "mpow_plan_destroy": (c.c_int, [P]),
         "mpow_run": (c.c_int, [P, P, c.c_int, c.c_int64, P, P, P]),
         "mpow_run_naive": (c.c_int, [P, P, c.c_int, c.c_int64, P, P, P]),
+        "mpow_run_noalloc": (c.c_int, [P, c.c_int, c.c_int64, P, P, P]),
         "mpow_expm": (c.c_int, [P, P, c.c_int, P, P, c.c_int, P]),
         "mpow_run_batched": (c.c_int, [P, c.c_int, P, P, P, P, P, P]),
         "mpow_last_device_error": (c.c_int, [P]),
@@ -229,6 +232,12 @@ def mpow_run_naive(plan: int, A: int, n: int, p: int, out: int, log2_scale: int 
                    stream: int | None) -> None:
     st = _load().mpow_run_naive(plan, A, int(n), int(p), out, log2_scale or None, stream or None)
     _check(st, "mpow_run_naive")
+
+
+def mpow_run_noalloc(A: int, n: int, p: int, out: int, log2_scale: int | None,
+                     stream: int | None) -> None:
+    st = _load().mpow_run_noalloc(A, int(n), int(p), out, log2_scale or None, stream or None)
+    _check(st, "mpow_run_noalloc")
 
 
 def mpow_expm(plan: int, A: int, n: int, out: int, log2_scale: int | None, squarings: int,

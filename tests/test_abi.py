@@ -86,6 +86,21 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.mpow_last_device_error(None) == 0
 
 
+def test_noalloc_rejects_without_device(lib):
+    # argument errors and sizes beyond the fixed workspace are reported before
+    # any device call (the pointers below are never dereferenced)
+    f = lib.mpow_run_noalloc
+    A, out = 1 << 20, 1 << 30
+    assert f(None, 16, 3, out, None, None) == mpow.MPOW_ERR_INVALID
+    assert f(A, 0, 3, out, None, None) == mpow.MPOW_ERR_INVALID
+    assert f(A, 16, -1, out, None, None) == mpow.MPOW_ERR_INVALID
+    assert f(A + 2, 16, 3, out, None, None) == mpow.MPOW_ERR_INVALID
+    assert f(A, 16, 3, A + 4, None, None) == mpow.MPOW_ERR_INVALID
+    n = mpow.MPOW_NOALLOC_MAX_N + 1
+    assert f(A, n, 3, A + 4 * n * n, None, None) == mpow.MPOW_ERR_UNSUPPORTED
+    assert mpow.MPOW_NOALLOC_MAX_N == 2048
+
+
 def test_plan_create_without_gpu_reports_device_error(lib):
     try:
         import torch
