@@ -246,28 +246,42 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
                              void *stream);
 
 /* Tile table of the batched kernel: table[b] is the tile shape used for
- * matrices with n in (16(b-1), 16b], b = 1..16 (table[0] is unused); shapes
- * 0 = 128x128, 1 = 64x64, 2 = 256x256 on 8 waves.  Every shape gives
- * bit-identical results; only speed differs.  A batch runs on one kernel
- * instance: the smallest that holds every shape it uses (without shape 0
- * or 2: a 64x64-only instance that keeps four workgroups per CU; with
- * shape 2: an instance of one 8-wave workgroup per CU); with shape 0 and
- * every matrix allowing 16-byte loads (n % 4 == 0, 16-byte aligned A), an
- * instance whose 128x128 and 64x64 tiles load straight into LDS (e.g.
- * n = 256 at 100 against 73 TFLOP/s).  The autotuner picks among shapes 0
- * and 1, timed on that instance.
+ * matrices with n in (16(b-1), 16b], b = 1..16 (table[0] is unused).
+ * Shapes 0 = 128x128, 1 = 64x64, 2 = 256x256 on 8 waves: each product is
+ * tiled, the running matrices pass through per-worker scratch in memory.
+ * Shapes 3 and 4: one workgroup computes the matrix's whole power with
+ * every product held in its accumulators (section 4.3's schedule with the
+ * operands staged in local memory, section 4.3.2); 3 keeps the base and the
+ * running matrix resident in LDS for n <= 128 (four waves and 32 KB up to
+ * n = 64, eight waves and 128 KB above) and streams K panels of both from
+ * scratch for n > 128; 4 always streams K panels (64 KB of LDS, two
+ * workgroups per CU, up to n = 128; 128 KB above).  Every shape gives
+ * bit-identical results; only speed differs.  A batch runs as one launch
+ * per group of matrices that share a kernel instance (at most five, in
+ * order on the stream): the tiled shapes on the smallest instance that
+ * holds every tiled shape used (without shape 0 or 2: a 64x64-only instance
+ * that keeps four workgroups per CU; with shape 2: one 8-wave workgroup per
+ * CU; with shape 0 and every such matrix allowing 16-byte loads, n % 4 == 0
+ * and a 16-byte aligned A, the instance whose tiles load straight into
+ * LDS), and each whole-power form on its own instance.
  * set = 0 copies the plan's table into table[0..16]; set = 1 replaces it.
  * len must be >= 17.
  * Errors: INVALID (plan NULL or without batch support, len < 17, a shape
- * outside 0..2). */
+ * outside 0..4). */
 mpow_status mpow_plan_tile_table(mpow_plan_t plan, int *table, int len, int set);
 
 #define MPOW_TUNE_FORCE 1u /* ignore an existing cache file */
 
 /* Autotuner (precedent: the per-problem tile choice of section 4.3.7): for
- * every size bucket up to min(max_n, 256) times each tile shape of the
- * batched kernel on a synthetic batch that fills all workers (p = 3) and keeps
- * the fastest in the plan's tile table.  If cache_path is non-NULL and holds
+ * every size bucket up to min(max_n, 256) times each of the five tile shapes
+ * of the batched kernel on a synthetic batch of that size that fills all
+ * workers twice (p = 100, eight products), run through mpow_run_batched's
+ * own grouping and launches.  Because a mixed batch runs one launch per
+ * kernel instance it needs, one after another, whole tables are then timed
+ * on a synthetic ragged batch (sizes uniform over the buckets, p
+ * log-uniform in [2, 1000]): the per-bucket winners, the table before
+ * tuning, and each single shape for all sizes; the fastest becomes the
+ * plan's tile table.  If cache_path is non-NULL and holds
  * a table written for the same GPU model (architecture and CU count), that
  * table is loaded instead (unless MPOW_TUNE_FORCE); a fresh table is written
  * there.  Synchronous; allocates temporary device memory (not on the run
@@ -295,7 +309,10 @@ mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel);
  * -1 for n < 1.  Below n = 768 the 32x32 tile with a 4-way K split (its
  * whole-K-in-LDS form up to n = 512); from n = 768 the LDS-DMA tile with the
  * best estimated rate for how its tile count fills the 256 CUs in whole
- * waves (section 4.3.7's tiled product, tile size chosen per n). */
+ * waves (section 4.3.7's tiled product, tile size chosen per n).  For
+ * n <= 64 mpow_run's binary schedule does not launch a product kernel at
+ * all: it runs the whole power in one workgroup (MPOW_KERNEL_POWER_WG); the
+ * kernel returned here is then the one of its naive and window forms. */
 int mpow_fp32_kernel_for(int n, int aligned);
 
 /* The last hipError_t value a call on this plan saw (0 if none). */
@@ -324,7 +341,8 @@ enum {
     MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18, /* float32 product, 32x32 tiles, K split over 4 waves, whole K in LDS (n <= 512) */
     MPOW_KERNEL_POWER_WG = 19, /* float32, n <= 128: the whole power in one launch of one
                                   8-wave workgroup, base and running matrix resident in
-                                  LDS (mpow_run only; timing counts G(p) 2 n^3 per launch) */
+                                  LDS (mpow_run only, its default for n <= 64; timing
+                                  counts G(p) 2 n^3 per launch) */
     MPOW_KERNEL_COUNT = 20
 };
 

@@ -2,6 +2,7 @@
 // tile shape on a synthetic batch that keeps all workers busy, and keeps the
 // fastest.  The paper chose its tile size per problem and per amount of local
 // memory by hand (section 4.3.7); here the choice is measured on the device.
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -14,8 +15,8 @@ using namespace mpow;
 namespace {
 
 constexpr int kBuckets = kTileBuckets;
-constexpr int kShapes = kBatchShapes;  // tile shape ids of the batched kernel
-constexpr int kTunedShapes = 2;        // the shapes the autotuner times (0, 1)
+constexpr int kShapes = kBatchShapes;  // tile shape ids of the batched kernel, all timed
+constexpr int64_t kTuneP = 100;        // power of the timing batches (8 products)
 
 struct DevGuard {
     int prev = -1;
@@ -143,38 +144,29 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
     if (st == MPOW_SUCCESS && hipMemcpy(in, host.data(), mat * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         st = MPOW_ERR_DEVICE;
 
-    BatchLaunch bl;
-    bl.desc = plan->batch.slot[0].desc;
-    bl.scratch = plan->batch.scratch;
-    bl.slot_floats = plan->batch.slot_floats;
-    BatchHeader *hdr = (BatchHeader *)plan->batch.slot[0].host;
-    BatchItem *items = (BatchItem *)(hdr + 1);
-    const size_t bytes = sizeof(BatchHeader) + (size_t)count * sizeof(BatchItem);
-
+    int before[kBuckets];
+    for (int b = 0; b < kBuckets; ++b) before[b] = plan->batch.cfg[b];
+    // Each bucket is timed on a uniform batch of its size through the same
+    // grouping and launches as a real batch, once per tile shape.
+    std::vector<const float *> Ap((size_t)count, in);
+    std::vector<float *> Op((size_t)count);
+    std::vector<int> nv((size_t)count);
+    std::vector<int64_t> pv((size_t)count, kTuneP);
+    for (int i = 0; i < count; ++i) Op[i] = out + (size_t)i * mat;
     for (int b = 1; st == MPOW_SUCCESS && b * 16 <= bmax; ++b) {
         const int n = b * 16;
+        for (int i = 0; i < count; ++i) nv[i] = n;
         float best = 1e30f;
-        int best_shape = plan->batch.cfg[b];
-        for (int shape = 0; shape < kTunedShapes && st == MPOW_SUCCESS; ++shape) {
-            // timed on the instance a mixed batch of 16-byte-loadable matrices
-            // runs on (the buffers here are 16-byte aligned, n a multiple of 16)
-            const int inst = batch_instance(1, true);
+        const int prev = plan->batch.cfg[b];
+        int best_shape = prev;
+        for (int shape = 0; shape < kShapes && st == MPOW_SUCCESS; ++shape) {
+            plan->batch.cfg[b] = shape;
             float t_min = 1e30f;
             for (int rep = 0; rep < 4 && st == MPOW_SUCCESS; ++rep) {
-                hdr->counter = 0;
-                hdr->count = count;
-                for (int i = 0; i < count; ++i) {
-                    items[i].A = in;
-                    items[i].out = out + (size_t)i * mat;
-                    items[i].scale = nullptr;
-                    items[i].p = 3;
-                    items[i].n = n;
-                    items[i].cfg = shape;
-                }
                 float ms = 0.f;
-                if (hipMemcpyAsync(plan->batch.slot[0].desc, plan->batch.slot[0].host, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-                    hipEventRecord(e0, s) != hipSuccess ||
-                    launch_batched(bl, plan->batch.workers[inst], inst, s) != hipSuccess ||
+                if (hipEventRecord(e0, s) != hipSuccess ||
+                    batch_enqueue(&plan->batch, count, Ap.data(), nv.data(), pv.data(), Op.data(),
+                                  nullptr, s, false, nullptr) != hipSuccess ||
                     hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                     st = MPOW_ERR_DEVICE;
@@ -187,8 +179,56 @@ mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_
                 best_shape = shape;
             }
         }
-        if (st == MPOW_SUCCESS) plan->batch.cfg[b] = best_shape;
+        plan->batch.cfg[b] = st == MPOW_SUCCESS ? best_shape : prev;
     }
+
+    // Per-bucket winners on uniform batches can split a mixed batch into
+    // several launches that run one after another, each ending in a tail of
+    // idle CUs.  So whole tables are also timed on a ragged batch (sizes
+    // uniform over the buckets, powers log-uniform in [2, 1000], fixed
+    // pseudo-random draws), and the fastest table is kept: the per-bucket
+    // one, the table before tuning, and one shape for every size.
+    if (st == MPOW_SUCCESS) {
+        const int nbk = bmax / 16;
+        for (int i = 0; i < count; ++i) {
+            x = x * 1664525u + 1013904223u;
+            nv[i] = 16 * (1 + (int)((x >> 8) % (uint32_t)nbk));
+            x = x * 1664525u + 1013904223u;
+            const double u = (double)(x >> 8) / 16777216.0;
+            pv[i] = (int64_t)(2.0 * std::exp(u * std::log(500.0)) + 0.5);
+        }
+        int tables[3 + kShapes][kBuckets];
+        int ntab = 0;
+        for (int b = 0; b < kBuckets; ++b) tables[0][b] = plan->batch.cfg[b];
+        for (int b = 0; b < kBuckets; ++b) tables[1][b] = before[b];
+        ntab = 2;
+        for (int shape = 0; shape < kShapes; ++shape, ++ntab)
+            for (int b = 0; b < kBuckets; ++b) tables[ntab][b] = b == 0 ? before[0] : shape;
+        float best = 1e30f;
+        int best_t = 0;
+        for (int t = 0; t < ntab && st == MPOW_SUCCESS; ++t) {
+            for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = tables[t][b];
+            float t_min = 1e30f;
+            for (int rep = 0; rep < 3 && st == MPOW_SUCCESS; ++rep) {
+                float ms = 0.f;
+                if (hipEventRecord(e0, s) != hipSuccess ||
+                    batch_enqueue(&plan->batch, count, Ap.data(), nv.data(), pv.data(), Op.data(),
+                                  nullptr, s, false, nullptr) != hipSuccess ||
+                    hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    st = MPOW_ERR_DEVICE;
+                    break;
+                }
+                if (rep > 0 && ms < t_min) t_min = ms;
+            }
+            if (t_min < best) {
+                best = t_min;
+                best_t = t;
+            }
+        }
+        for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = tables[st == MPOW_SUCCESS ? best_t : 1][b];
+    }
+    if (st == MPOW_SUCCESS && batch_wait_all(&plan->batch) != hipSuccess) st = MPOW_ERR_DEVICE;
     if (st != MPOW_SUCCESS) plan->last_error = (int)hipGetLastError();
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -212,6 +212,17 @@ struct BatchInst {
                   : F32TileLds<TB, TB>::B_FLOATS;
 };
 
+// Next matrix of the launch's group (descriptors begin[g] .. end[g] - 1),
+// claimed by thread 0 and broadcast; -1 once the group's queue is empty.
+// Contains barriers.
+__device__ __forceinline__ int claim_item(BatchHeader *hdr, int g, int *claimed) {
+    if (threadIdx.x == 0) *claimed = hdr->begin[g] + atomicAdd(&hdr->counter[g], 1);
+    __syncthreads();
+    const int it = *claimed;
+    __syncthreads();
+    return it < hdr->end[g] ? it : -1;
+}
+
 // The worker loop: claim matrices until the queue is empty and compute each
 // one's whole power; product(cfg, X, eX, Y, eY, C, n, vec) computes one
 // product in the workgroup and returns its sum of squares.
@@ -220,16 +231,12 @@ __device__ __forceinline__ void run_jobs(const BatchLaunch &b, double *red, int 
                                          ProductFn product) {
     BatchHeader *hdr = (BatchHeader *)b.desc;
     const BatchItem *items = (const BatchItem *)(hdr + 1);
-    const int count = hdr->count;
     float *S0 = b.scratch + (int64_t)blockIdx.x * 2 * b.slot_floats;
     float *S1 = S0 + b.slot_floats;
 
     for (;;) {
-        if (threadIdx.x == 0) *claimed = atomicAdd(&hdr->counter, 1);
-        __syncthreads();
-        const int it = *claimed;
-        __syncthreads();
-        if (it >= count) break;
+        const int it = claim_item(hdr, b.group, claimed);
+        if (it < 0) break;
 
         const BatchItem item = items[it];
         const int n = item.n;
@@ -331,26 +338,57 @@ __global__ __launch_bounds__(256) void batched_dma_kernel(BatchLaunch b) {
     run_jobs<256>(b, red, &claimed, product);
 }
 
-// Instance 4: every matrix's whole power in one 8-wave workgroup (power_wg.h):
-// LDS-resident for n <= 128, K panels streamed from the worker's scratch
-// (2 npad^2 floats) above.  One workgroup per CU (128 KB of LDS).
-__global__ __launch_bounds__(WG_NT, 1) void batched_wg_kernel(BatchLaunch b) {
-    __shared__ __attribute__((aligned(16))) float L0[WG_STAGE];
-    __shared__ __attribute__((aligned(16))) float L1[WG_STAGE];
-    __shared__ double red[WG_NT];
+// Instances 4-7: every matrix's whole power in one workgroup (power_wg.h).
+// 4: resident, row stride 64, four waves (n <= 64; 32 KB of LDS, several
+// workgroups per CU); 5: resident, row stride 128, eight waves (n <= 128;
+// 128 KB, one per CU); 6: K panels streamed from the worker's scratch
+// (2 npad^2 floats), eight waves (n <= 256; 128 KB, one per CU); 7: the
+// panel form for n <= 128 (64 KB, two per CU).
+// Workgroups per CU the resident instances are compiled for: four of the
+// 32 KB form (n <= 64), one of the 128 KB form.
+template <int LD>
+struct ResPerCu {
+    static constexpr int value = LD == 64 ? 4 : 1;
+};
+
+template <int LD, int NW>
+__global__ __launch_bounds__(NW * 64, ResPerCu<LD>::value) void batched_wg_res_kernel(BatchLaunch b) {
+    __shared__ __attribute__((aligned(16))) float LX[WgResLds<LD>::FLOATS];
+    __shared__ __attribute__((aligned(16))) float LA[WgResLds<LD>::FLOATS];
+    __shared__ double red[NW];
     __shared__ int claimed;
     BatchHeader *hdr = (BatchHeader *)b.desc;
     const BatchItem *items = (const BatchItem *)(hdr + 1);
-    const int count = hdr->count;
+    for (;;) {
+        const int it = claim_item(hdr, b.group, &claimed);
+        if (it < 0) break;
+        const BatchItem item = items[it];
+        wg_power_resident<LD, NW>(item.A, item.n, item.p, item.out, item.scale, LX, LA, red);
+    }
+}
+
+// Waves of the panel instances: sixteen for n <= 256 (four blocks each),
+// eight for n <= 128 (two workgroups per CU).
+template <int NPMAX>
+struct PanelWaves {
+    static constexpr int NW = NPMAX == 256 ? 16 : 8;
+};
+
+template <int NPMAX>
+__global__ __launch_bounds__(PanelWaves<NPMAX>::NW * 64) void batched_wg_panel_kernel(BatchLaunch b) {
+    constexpr int NW = PanelWaves<NPMAX>::NW;
+    __shared__ __attribute__((aligned(16))) float L0[WgPanelLds<NPMAX>::STAGE];
+    __shared__ __attribute__((aligned(16))) float L1[WgPanelLds<NPMAX>::STAGE];
+    __shared__ double red[NW];
+    __shared__ int claimed;
+    BatchHeader *hdr = (BatchHeader *)b.desc;
+    const BatchItem *items = (const BatchItem *)(hdr + 1);
     float *scratch = b.scratch + (int64_t)blockIdx.x * 2 * b.slot_floats;
     for (;;) {
-        if (threadIdx.x == 0) claimed = atomicAdd(&hdr->counter, 1);
-        __syncthreads();
-        const int it = claimed;
-        __syncthreads();
-        if (it >= count) break;
+        const int it = claim_item(hdr, b.group, &claimed);
+        if (it < 0) break;
         const BatchItem item = items[it];
-        wg_power<false>(item.A, item.n, item.p, item.out, item.scale, scratch, L0, L1, red);
+        wg_power_panel<NPMAX, NW>(item.A, item.n, item.p, item.out, item.scale, scratch, L0, L1, red);
     }
 }
 
@@ -366,31 +404,46 @@ int batched_cfg_for(int n) {
 int batched_occupancy(int inst) {
     int blocks = 0;
     hipError_t e;
-    if (inst == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_wg_kernel, WG_NT, 0);
-    else if (inst == 3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_dma_kernel, 256, 0);
-    else if (inst == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<2>, 512, 0);
-    else if (inst == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<1>, 256, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<0>, 256, 0);
+    switch (inst) {
+        case 7:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_wg_panel_kernel<128>, 512, 0);
+            break;
+        case 6:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_wg_panel_kernel<256>,
+                                                             PanelWaves<256>::NW * 64, 0);
+            break;
+        case 5:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_wg_res_kernel<128, 8>, 512, 0);
+            break;
+        case 4:
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_wg_res_kernel<64, 4>, 256, 0);
+            break;
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_dma_kernel, 256, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<2>, 512, 0); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<1>, 256, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_kernel<0>, 256, 0); break;
+    }
     if (e != hipSuccess) return 1;
     return blocks < 1 ? 1 : blocks;
 }
 
+bool batched_uses_scratch(int inst) { return inst != 4 && inst != 5; }
+
 hipError_t launch_batched(const BatchLaunch &b, int grid, int inst, hipStream_t s) {
-    if (inst == 4)
-        hipLaunchKernelGGL(batched_wg_kernel, dim3(grid), dim3(WG_NT), 0, s, b);
-    else if (inst == 3)
-        hipLaunchKernelGGL(batched_dma_kernel, dim3(grid), dim3(256), 0, s, b);
-    else if (inst == 2)
-        hipLaunchKernelGGL(batched_kernel<2>, dim3(grid), dim3(512), 0, s, b);
-    else if (inst == 1)
-        hipLaunchKernelGGL(batched_kernel<1>, dim3(grid), dim3(256), 0, s, b);
-    else
-        hipLaunchKernelGGL(batched_kernel<0>, dim3(grid), dim3(256), 0, s, b);
+    switch (inst) {
+        case 7: hipLaunchKernelGGL(batched_wg_panel_kernel<128>, dim3(grid), dim3(512), 0, s, b); break;
+        case 6:
+            hipLaunchKernelGGL(batched_wg_panel_kernel<256>, dim3(grid), dim3(PanelWaves<256>::NW * 64), 0,
+                               s, b);
+            break;
+        case 5: hipLaunchKernelGGL((batched_wg_res_kernel<128, 8>), dim3(grid), dim3(512), 0, s, b); break;
+        case 4: hipLaunchKernelGGL((batched_wg_res_kernel<64, 4>), dim3(grid), dim3(256), 0, s, b); break;
+        case 3: hipLaunchKernelGGL(batched_dma_kernel, dim3(grid), dim3(256), 0, s, b); break;
+        case 2: hipLaunchKernelGGL(batched_kernel<2>, dim3(grid), dim3(512), 0, s, b); break;
+        case 1: hipLaunchKernelGGL(batched_kernel<1>, dim3(grid), dim3(256), 0, s, b); break;
+        case 0: hipLaunchKernelGGL(batched_kernel<0>, dim3(grid), dim3(256), 0, s, b); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

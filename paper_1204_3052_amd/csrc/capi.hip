@@ -116,8 +116,7 @@ mpow_status mpow_plan_create(mpow_plan_t *out_plan, int device, int max_n, int m
     if (!guard.ok) return MPOW_ERR_DEVICE;
     int workers[kBatchInstances] = {};
     if (max_batch > 0 && !batch_workers_for(device, workers)) return MPOW_ERR_DEVICE;
-    int wmax = 0;
-    for (int w : workers) wmax = w > wmax ? w : wmax;
+    const int wmax = batch_scratch_workers(workers);
     const size_t ws_bytes = workspace_bytes(max_n, mode);
     const size_t b_bytes = max_batch > 0 ? batch_device_bytes(max_batch, batch_bmax(max_n), wmax) : 0;
     // mpow_expm's Taylor polynomial and norm exponent

@@ -127,8 +127,12 @@ constexpr int kPowerWgMaxN = 128;
 hipError_t launch_power_wg(const float *A, int n, int64_t p, float *out, double *log2_scale,
                            hipStream_t s);
 // mpow_run's float32 path takes launch_power_wg for n up to this size unless
-// a product kernel is forced.
-constexpr int kPowerWgAutoMaxN = 0;
+// a product kernel is forced.  Measured per power (p = 64 / 1000): n = 16-64
+// one workgroup takes 19-46 us against 40-88 us for one launch per product;
+// at n = 96 and 128 it is slower (53 / 83 us against 43 / 42 us at p = 64),
+// because one CU's MFMA rate bounds it (a 128^3 product is 6.8 us on one CU
+// at peak, about what a launched product costs on many CUs).
+constexpr int kPowerWgAutoMaxN = 64;
 // The naive method: p - 1 chained float32 products X <- X.A (p <= MPOW_NAIVE_MAX_P).
 hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                                double *log2_scale, hipStream_t s, TimingSink *timing);
@@ -228,30 +232,47 @@ hipError_t launch_finish(const float *C, int n, const double *partC, int nPartC,
 
 // Descriptors the host fills (sorted by work), after a header holding the
 // claim counter; per-worker scratch.
+// A batch runs as up to kBatchGroups launches, one per kernel instance it
+// needs; group g's descriptors are begin[g] .. end[g] - 1, claimed in order
+// through counter[g] (the host copy resets the counters to 0).
+constexpr int kBatchGroups = 5;
 struct BatchHeader {
-    int counter;  // next descriptor to claim; the host copy resets it to 0
+    int counter[kBatchGroups];
+    int begin[kBatchGroups];
+    int end[kBatchGroups];
     int count;
-    int pad[2];
 };
+static_assert(sizeof(BatchHeader) % 16 == 0, "descriptors after the header stay 16-byte aligned");
 struct BatchItem {
     const float *A;
     float *out;
     double *scale;  // null: no log2 scale for this matrix
     int64_t p;
     int n;
-    int cfg;        // tile shape id (0: 128x128, 1: 64x64)
+    int cfg;        // tile shape id (0: 128x128, 1: 64x64, 2: 256x256, 3-4: whole power)
 };
 struct BatchLaunch {
     void *desc;           // BatchHeader followed by the items
     float *scratch;       // grid * 2 * slot_floats floats
     int64_t slot_floats;  // floats per scratch buffer (max batched n squared)
+    int group = 0;        // the descriptor group this launch works through
 };
 constexpr int kBatchMaxN = 256;
 constexpr int kTileBuckets = kBatchMaxN / 16 + 1;  // bucket b holds n in (16(b-1), 16b]
-constexpr int kBatchShapes = 4;   // tile shape ids of the batched kernel (3: whole-power workgroup)
-// 0: 64x64; 1: 128x128 + 64x64; 2: 256x256; 3: LDS-DMA 128/64; 4: whole power
-// per 8-wave workgroup (power_wg.h)
-constexpr int kBatchInstances = 5;
+// Tile shape ids: 0 = 128x128, 1 = 64x64, 2 = 256x256 (tiled products
+// through per-worker scratch), 3 = the whole power in one workgroup with its
+// operands resident in LDS where n <= 128 (streamed panels above), 4 = the
+// whole power in one workgroup with streamed panels.
+constexpr int kBatchShapes = 5;
+// Kernel instances: 0: 64x64; 1: 128x128 + 64x64; 2: 256x256; 3: LDS-DMA
+// 128/64; whole power per workgroup (power_wg.h): 4 resident n <= 64,
+// 5 resident n <= 128, 6 panels n <= 256, 7 panels n <= 128
+constexpr int kBatchInstances = 8;
+// Instances that use the workers' scratch buffers (not the resident ones).
+bool batched_uses_scratch(int inst);
+// Workers whose scratch a context must hold: the largest grid of the
+// instances that use scratch (launch groups run one after another).
+int batch_scratch_workers(const int workers[kBatchInstances]);
 int batched_cfg_for(int n);
 // Resident workers per CU of kernel instance inst (0: 64x64 only, 1: 128x128
 // and 64x64, 2: 256x256 and 128x128 with 8 waves).
@@ -270,7 +291,7 @@ struct BatchSlot {
     void *host = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_count = -1;
-    int graph_inst = -1;
+    int graph_inst[kBatchGroups] = {-1, -1, -1, -1, -1};  // instance of each group's launch (-1: none)
     hipEvent_t done = nullptr;
     bool pending = false;
 };

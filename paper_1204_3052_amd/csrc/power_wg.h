@@ -1,7 +1,7 @@
-// A whole power A^p of one matrix (n <= 256) computed by one workgroup of
-// eight waves: the paper's repeated-squaring schedule (section 4.3) with its
-// operands staged in the workgroup's local memory (sections 4.3.2, 4.3.6),
-// every product held whole in the waves' accumulators.
+// A whole power A^p of one matrix (n <= 256) computed by one workgroup: the
+// paper's repeated-squaring schedule (section 4.3) with its operands staged
+// in the workgroup's local memory (sections 4.3.2, 4.3.6), every product
+// held whole in the waves' accumulators.
 //
 // Why one workgroup and whole products: at these sizes a product is 2n^3
 // flops (at most 34 MFLOP), a few microseconds of one CU's MFMA pipes, which
@@ -11,28 +11,38 @@
 // norm is a reduction over its own accumulators.
 //
 //  - The product C = X Y is cut into 32 x 32 blocks (nb = ceil(n / 32) per
-//    side); wave w owns blocks w, w + 8, w + 16, ... in row-major block
-//    order (at most 8 blocks, 128 accumulator registers per lane), so the
-//    waves' shares differ by at most one block.  Each block is accumulated
-//    with v_mfma_f32_32x32x2_f32 in the k order of the other float32 tiles
-//    (K tiles of 32 ascending, lane half h taking k = 16h + 4q + t), so the
-//    products carry the same bits as theirs.
-//  - n <= 128 (resident): the normalised base 2^-eA A and the running matrix
-//    X stay in LDS for the whole power (two 128 x 128 float arrays, 128 KB).
-//    Element (r, c) sits at r * 128 + 4 ((c / 4) ^ g(r)) + c % 4 with
-//    g(r) = (r % 16) ^ (8 * ((r / 16) % 2)): the left operand's 16-byte reads
-//    (rows r0 .. r0 + 15 of one chunk) and the right operand's 4-byte reads
-//    (rows k and k + 16, 32 columns each) are free of bank conflicts.  After
-//    each product the waves reduce the sum of squares of C, derive
+//    side), each accumulated by one wave with v_mfma_f32_32x32x2_f32 in the
+//    k order of the other float32 tiles (K tiles of 32 ascending, lane half
+//    h taking k = 16h + 4q + t), so the products carry the same bits as
+//    theirs.
+//  - Resident form (n <= LD, LD = 64 or 128): the normalised base 2^-eA A
+//    and the running matrix X stay in LDS for the whole power (two LD x LD
+//    float arrays: 32 KB for LD = 64, 128 KB for LD = 128).  Element (r, c)
+//    sits at r * LD + 4 ((c / 4) ^ g(r)) + c % 4 with
+//    g(r) = (r % 16) ^ (8 * ((r / 16) % 2)): the left operand's 16-byte
+//    reads (rows r0 .. r0 + 15 of one chunk) and the right operand's 4-byte
+//    reads (rows k and k + 16, 32 columns each) are free of bank conflicts.
+//    Wave w owns blocks w, w + NW, ... in row-major block order.  After each
+//    product the waves reduce the sum of squares of C, derive
 //    e = floor(log2 ||C||_F), and write C * 2^-e over X.
-//  - 128 < n <= 256 (panel): the running matrix and 2^-eA A live in two
+//  - Panel form (n <= NPMAX): the running matrix and 2^-eA A live in two
 //    n_pad x n_pad float arrays in memory (n_pad = 32 nb, zero padded, the
 //    workgroup's own scratch), and each product streams K panels of 32
 //    (n_pad x 32 of X, 32 x n_pad of Y) into two LDS stages by LDS-DMA
 //    buffer loads, the next panel loading while the current one feeds the
-//    MFMAs.  Each element of X and Y is read once per product.  Layouts as
-//    the LDS-DMA tiles: X panel chunk c of row r at c ^ ((r / 2) % 8), Y panel
-//    rows with bit 4 of k set swapping their 32-float halves.
+//    MFMAs; each element of X and Y is read once per product.  The block
+//    grid in column-major order is cut into NW contiguous ranges of
+//    floor or ceil (nb^2 / NW) blocks (NW = 8 or 16 waves), range r going
+//    to the wave of rank r (the waves that share a SIMD hold consecutive
+//    ranges, so the SIMDs carry equal work): a wave's blocks then lie in at
+//    most two block columns, and it reads each right-operand value once for
+//    all of them.  For n <= 256 sixteen waves hold at most four blocks each
+//    (64 accumulator registers), which leaves registers to read the next
+//    step's operands while the MFMAs of the current one run.
+//    The number of blocks selects a fully unrolled instance of the K loop.
+//    Layouts as the LDS-DMA tiles: X panel chunk c of row r at
+//    c ^ ((r / 2) % 8), Y panel rows with bit 4 of k set swapping their
+//    32-float halves.
 //  - Scaling: operands are always the normalised matrices, so a product's
 //    sums are those of the other kernels with scaled operands (exact powers
 //    of two); s follows s <- 2 (s + eX) for a square and s <- s + eX + eA for
@@ -45,366 +55,571 @@
 
 namespace mpow {
 
-constexpr int WG_NT = 512;         // threads of the workgroup (8 waves)
-constexpr int WG_NW = 8;
-constexpr int WG_RES_MAX_N = 128;  // LDS-resident up to this n
-constexpr int WG_MAX_N = 256;      // panel path up to this n
-constexpr int WG_RES_LD = 128;     // LDS row stride of a resident matrix (floats)
-constexpr int WG_STAGE = 2 * 256 * 32;  // floats of one panel stage (X panel, then Y panel)
-static_assert(WG_STAGE == WG_RES_LD * WG_RES_LD, "a stage array holds one resident matrix");
+constexpr int WG_RES_MAX_N = 128;  // resident form up to this n
+constexpr int WG_MAX_N = 256;      // panel form up to this n
 
-// Row stride of the panel path's matrices in memory.
+// Row stride of the panel form's matrices in memory.
 __host__ __device__ constexpr int wg_npad(int n) { return (n + 31) / 32 * 32; }
+
+// LDS of the resident form: two LD x LD float arrays.
+template <int LD>
+struct WgResLds {
+    static constexpr int FLOATS = LD * LD;
+};
+// LDS of the panel form: one stage holds an NPMAX x 32 X panel and a
+// 32 x NPMAX Y panel; two stages alternate.
+template <int NPMAX>
+struct WgPanelLds {
+    static constexpr int STAGE = 2 * NPMAX * 32;
+};
 
 namespace wgdetail {
 
 __device__ __forceinline__ int res_swz(int r) { return (r & 15) ^ (((r >> 4) & 1) << 3); }
+template <int LD>
 __device__ __forceinline__ int res_idx(int r, int c) {
-    return r * WG_RES_LD + 4 * ((c >> 2) ^ res_swz(r)) + (c & 3);
+    return r * LD + 4 * ((c >> 2) ^ res_swz(r)) + (c & 3);
 }
 
-// Block j of this wave: row and column of the block grid.
-struct Blocks {
-    int cnt;
-    int bi[8], bj[8];
-};
-__device__ __forceinline__ Blocks wave_blocks(int nb, int wave) {
-    Blocks b;
-    const int T = nb * nb;
-    b.cnt = wave < T ? (T - wave + WG_NW - 1) / WG_NW : 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int t = wave + WG_NW * j;
-        b.bi[j] = t / nb;
-        b.bj[j] = t % nb;
-    }
-    return b;
-}
-
-// Sum of squares of the valid part (row, col < n) of this wave's blocks,
-// reduced over the workgroup in a fixed order; every thread gets it.
-template <int MB>
-__device__ __forceinline__ double wg_block_sumsq(const v16f (&acc)[MB], const Blocks &b, int n,
-                                                 double *red) {
+// Fixed-order workgroup sum of one double per thread (wave trees, then the
+// waves in order); every thread gets it.  Contains a barrier; `red` holds NW
+// doubles and must not be written again before the next barrier.
+template <int NW>
+__device__ __forceinline__ double wg_sum(double v, double *red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int h = lane >> 5, l32 = lane & 31;
-    double ss = 0.0;
-#pragma unroll
-    for (int j = 0; j < MB; ++j) {
-        if (j < b.cnt) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = b.bi[j] * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int col = b.bj[j] * 32 + l32;
-                if (row < n && col < n) ss += (double)acc[j][r] * (double)acc[j][r];
-            }
-        }
-    }
-    ss = wave_sum_lane0(ss);
-    if (lane == 0) red[wave] = ss;
+    v = wave_sum_lane0(v);
+    if (lane == 0) red[wave] = v;
     __syncthreads();
     double S = 0.0;
 #pragma unroll
-    for (int w = 0; w < WG_NW; ++w) S += red[w];
+    for (int w = 0; w < NW; ++w) S += red[w];
     return S;
 }
 
-// Writes this wave's blocks of the final C to out (n x n, row-major):
-// C * 2^-e with *scale = s + e (scale non-null), else C * 2^s rounded to
-// float32 through float64.
-template <int MB>
-__device__ __forceinline__ void wg_write_out(const v16f (&acc)[MB], const Blocks &b, int n,
-                                             float *out, double *scale, double S, int e, double s) {
-    const int lane = threadIdx.x & 63;
-    const int h = lane >> 5, l32 = lane & 31;
-    const PowScale f = pow2_neg(e);
-    double sc = s;
-    sc = sc > 4000.0 ? 4000.0 : (sc < -4000.0 ? -4000.0 : sc);
-    const int si = (int)sc;
+// Sum of squares of the valid part (row, col < n) of one 32 x 32 block.
+__device__ __forceinline__ double block_sumsq(const v16f &acc, int bi, int bj, int n) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+    const int col = bj * 32 + l32;
+    double ss = 0.0;
 #pragma unroll
-    for (int j = 0; j < MB; ++j) {
-        if (j < b.cnt) {
+    for (int r = 0; r < 16; ++r) {
+        const int row = bi * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (row < n && col < n) ss += (double)acc[r] * (double)acc[r];
+    }
+    return ss;
+}
+
+// Writes the valid part of one block of the final C to out (n x n,
+// row-major): C * 2^-e (scaled) or C * 2^si rounded through float64.
+__device__ __forceinline__ void block_write_out(const v16f &acc, int bi, int bj, int n, float *out,
+                                                bool scaled, PowScale f, int si) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+    const int col = bj * 32 + l32;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = b.bi[j] * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int col = b.bj[j] * 32 + l32;
-                if (row < n && col < n) {
-                    const float v = acc[j][r];
-                    out[(int64_t)row * n + col] = scale ? v * f.a * f.b : (float)ldexp((double)v, si);
+    for (int r = 0; r < 16; ++r) {
+        const int row = bi * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (row < n && col < n)
+            out[(int64_t)row * n + col] =
+                scaled ? acc[r] * f.a * f.b : (float)ldexp((double)acc[r], si);
+    }
+}
+
+// Sum of squares (float64) of an n x n matrix in memory by the workgroup of
+// NT threads, fixed order (16-byte loads when n % 4 == 0 and M is 16-byte
+// aligned, eight in flight per thread); every thread gets it.  Contains
+// barriers; `red` holds NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ double matrix_sumsq(const float *__restrict__ M, int n, double *red) {
+    const int64_t total = (int64_t)n * n;
+    double acc = 0.0;
+    constexpr int U = 8;
+    if ((n & 3) == 0 && ((uintptr_t)M & 15) == 0) {
+        const f4 *M4 = (const f4 *)M;
+        const int64_t t4 = total / 4;
+        for (int64_t b = threadIdx.x; b < t4; b += NT * U) {
+            f4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = b + (int64_t)u * NT;
+                v[u] = i < t4 ? M4[i] : f4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc += (double)v[u][c] * (double)v[u][c];
+        }
+    } else {
+        for (int64_t b = threadIdx.x; b < total; b += NT * U) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = b + (int64_t)u * NT;
+                v[u] = i < total ? M[i] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += (double)v[u] * (double)v[u];
+        }
+    }
+    const double S = wg_sum<NT / 64>(acc, red);
+    __syncthreads();  // `red` is free again
+    return S;
+}
+
+// The normalised base 2^-eA A, zero padded to npad x npad: store(r, c, v)
+// receives four consecutive columns c .. c + 3 (c % 4 == 0) of row r.  With
+// n % 4 == 0 and a 16-byte aligned A the input is read by 16-byte loads,
+// four in flight per thread.
+template <int NT, typename Store4>
+__device__ __forceinline__ void copy_base_padded(const float *__restrict__ A, int n, int npad,
+                                                 PowScale f, Store4 store) {
+    const int q = npad / 4;
+    const int total4 = npad * q;
+    constexpr int U = 4;
+    if ((n & 3) == 0 && ((uintptr_t)A & 15) == 0) {
+        const f4 *A4 = (const f4 *)A;
+        const int nq = n / 4;
+        for (int b = threadIdx.x; b < total4; b += NT * U) {
+            f4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = b + u * NT;
+                const int r = i / q, c4 = i - r * q;
+                v[u] = (i < total4 && r < n && c4 < nq) ? A4[r * nq + c4] * f.a * f.b
+                                                          : f4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = b + u * NT;
+                if (i < total4) {
+                    const int r = i / q;
+                    store(r, 4 * (i - r * q), v[u]);
                 }
             }
         }
+    } else {
+        for (int i = threadIdx.x; i < total4; i += NT) {
+            const int r = i / q, c = 4 * (i - r * q);
+            f4 v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                v[k] = (r < n && c + k < n) ? A[(int64_t)r * n + c + k] * f.a * f.b : 0.f;
+            store(r, c, v);
+        }
     }
-    if (scale && threadIdx.x == 0) *scale = (S == 0.0) ? 0.0 : s + (double)e;
 }
 
-// One product of the resident path: acc = X Y with X = left and Y = right,
-// both resident n_pad x n_pad matrices (nb blocks per side).
-template <int MB>
-__device__ __forceinline__ void res_product(v16f (&acc)[MB], const Blocks &b, int nb,
-                                            const float *left, const float *right) {
+// The first steps shared by both forms: p = 0 (identity) and p = 1 (A, or
+// A * 2^-eA with scale eA) are written out here and return false; otherwise
+// *SA and *eA are the input's sum of squares and exponent.
+template <int NT>
+__device__ __forceinline__ bool power_head(const float *A, int n, int64_t p, float *out,
+                                           double *scale, double *red, double *SA, int *eA) {
+    const int tid = threadIdx.x;
+    const int64_t total = (int64_t)n * n;
+    if (p == 0) {
+        for (int64_t i = tid; i < total; i += NT) {
+            const int64_t r = i / n, c = i - r * n;
+            out[i] = (r == c) ? 1.0f : 0.0f;
+        }
+        if (scale && tid == 0) *scale = 0.0;
+        __syncthreads();
+        return false;
+    }
+    *SA = matrix_sumsq<NT>(A, n, red);
+    *eA = exponent_of_sumsq(*SA);
+    if (p == 1) {
+        // each element is read and written by the same thread, so out may be A
+        const PowScale f = pow2_neg(*eA);
+        for (int64_t i = tid; i < total; i += NT) out[i] = scale ? A[i] * f.a * f.b : A[i];
+        if (scale && tid == 0) *scale = (*SA == 0.0) ? 0.0 : (double)*eA;
+        __syncthreads();
+        return false;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------ resident form
+
+// One product of the resident form: acc = X Y with X = left, Y = right
+// (resident, row stride LD, nb blocks per side); the wave owns CNT blocks,
+// wave + NW j.
+template <int LD, int NW, int CNT, int MB>
+__device__ __forceinline__ void res_product(v16f (&acc)[MB], int nb, int wave, const float *left,
+                                            const float *right) {
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
     for (int j = 0; j < MB; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+    int bi[MB], bj[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        const int t = wave + NW * j;
+        bi[j] = t / nb;
+        bj[j] = t - bi[j] * nb;
+    }
     for (int kt = 0; kt < nb; ++kt) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             f4 a[MB];
             float bv[MB][4];
 #pragma unroll
-            for (int j = 0; j < MB; ++j) {
-                if (j < b.cnt) {
-                    const int row = b.bi[j] * 32 + l32;
-                    a[j] = *(const f4 *)(left + row * WG_RES_LD +
-                                         4 * ((8 * kt + 4 * h + q) ^ res_swz(row)));
+            for (int j = 0; j < CNT; ++j) {
+                const int row = bi[j] * 32 + l32;
+                a[j] = *(const f4 *)(left + row * LD + 4 * ((8 * kt + 4 * h + q) ^ res_swz(row)));
 #pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        bv[j][t] = right[res_idx(32 * kt + 16 * h + 4 * q + t, b.bj[j] * 32 + l32)];
-                }
+                for (int t = 0; t < 4; ++t)
+                    bv[j][t] = right[res_idx<LD>(32 * kt + 16 * h + 4 * q + t, bj[j] * 32 + l32)];
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int j = 0; j < MB; ++j)
-                    if (j < b.cnt)
-                        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j][t], bv[j][t], acc[j], 0,
-                                                                      0, 0);
+                for (int j = 0; j < CNT; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j][t], bv[j][t], acc[j], 0, 0, 0);
         }
     }
 }
 
-// One product of the panel path: acc = X Y with X, Y n_pad x n_pad float
-// matrices in memory (row stride n_pad, zero padded), K panels streamed
-// through L0 / L1.  Ends with a workgroup barrier after the last panel.
-template <int MB>
-__device__ __forceinline__ void panel_product(v16f (&acc)[MB], const Blocks &b, int npad,
-                                              const float *X, const float *Y, float *L0,
-                                              float *L1) {
-    const int tid = threadIdx.x, lane = tid & 63;
+// The power's products for a wave with CNT blocks; see wg_power_resident.
+template <int LD, int NW, int CNT, int MB>
+__device__ __forceinline__ void res_power_body(int n, int64_t p, float *out, double *scale,
+                                               float *LX, float *LA, double *red, int eA,
+                                               int wave) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+    const int nb = wg_npad(n) / 32;
+    int bi[MB], bj[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        const int t = wave + NW * j;
+        bi[j] = t / nb;
+        bj[j] = t - bi[j] * nb;
+    }
+    const int top = 63 - __clzll((unsigned long long)p);
+    int eX = eA;
+    double s = 0.0, S = 0.0;
+    bool first = true;
+    v16f acc[MB];
+    for (int bit = top - 1; bit >= 0; --bit) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool mul = pass == 1;
+            if (mul && !((p >> bit) & 1)) break;
+            const bool last = bit == 0 && (mul || !(p & 1));
+            const float *left = first ? LA : LX;
+            res_product<LD, NW, CNT, MB>(acc, nb, wave, left, mul ? LA : left);
+            first = false;
+            double ss = 0.0;
+#pragma unroll
+            for (int j = 0; j < CNT; ++j) ss += block_sumsq(acc[j], bi[j], bj[j], n);
+            S = wg_sum<NW>(ss, red);  // barrier: X fully read
+            s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
+            eX = exponent_of_sumsq(S);
+            if (last) break;
+            // C * 2^-e over the running matrix (its padding stays zero)
+            const PowScale f = pow2_neg(eX);
+#pragma unroll
+            for (int j = 0; j < CNT; ++j) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = bi[j] * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                    LX[res_idx<LD>(row, bj[j] * 32 + l32)] = acc[j][r] * f.a * f.b;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double sc = s;
+    sc = sc > 4000.0 ? 4000.0 : (sc < -4000.0 ? -4000.0 : sc);
+    const PowScale f = pow2_neg(eX);
+#pragma unroll
+    for (int j = 0; j < CNT; ++j)
+        block_write_out(acc[j], bi[j], bj[j], n, out, scale != nullptr, f, (int)sc);
+    if (scale && threadIdx.x == 0) *scale = (S == 0.0) ? 0.0 : s + (double)eX;
+}
+
+}  // namespace wgdetail
+
+// A^p of one n x n matrix, 1 <= n <= LD, by the calling workgroup of NW
+// waves (all of which must call it), base and running matrix resident in
+// LDS: LX and LA hold LD * LD floats each, `red` NW doubles.  out may be A.  Contains barriers; returns with the workgroup synchronised.
+template <int LD, int NW>
+__device__ __forceinline__ void wg_power_resident(const float *A, int n, int64_t p, float *out, double *scale,
+                                  float *LX, float *LA, double *red) {
+    using namespace wgdetail;
+    constexpr int NT = NW * 64;
+    constexpr int MB = ((LD / 32) * (LD / 32) + NW - 1) / NW;
+    static_assert(MB >= 1 && MB <= 2, "resident forms hold at most two blocks per wave");
+    const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double SA;
+    int eA;
+    if (!power_head<NT>(A, n, p, out, scale, red, &SA, &eA)) return;
+
+    const int npad = wg_npad(n), nb = npad / 32;
+    const PowScale fa = pow2_neg(eA);
+    // the normalised base, zero padded to npad (a 4-column group of a row is
+    // one 16-byte chunk of the swizzled layout)
+    copy_base_padded<NT>(A, n, npad, fa, [&](int r, int c, f4 v) {
+        *(f4 *)(LA + res_idx<LD>(r, c)) = v;
+    });
+    __syncthreads();
+
+    const int T = nb * nb;
+    const int cnt = wave < T ? (T - wave + NW - 1) / NW : 0;
+    // every wave takes part in the barriers of every product, whatever its count
+    switch (cnt) {
+        case 0: res_power_body<LD, NW, 0, MB>(n, p, out, scale, LX, LA, red, eA, wave); break;
+        case 1: res_power_body<LD, NW, 1, MB>(n, p, out, scale, LX, LA, red, eA, wave); break;
+        default:
+            if constexpr (MB >= 2) res_power_body<LD, NW, 2, MB>(n, p, out, scale, LX, LA, red, eA, wave);
+            break;
+    }
+    __syncthreads();  // LDS and `red` may be reused by the caller
+}
+
+// --------------------------------------------------------------- panel form
+
+namespace wgdetail {
+
+// K panel kt of X and Y (npad x npad in memory, row stride npad) into stage
+// `st` by LDS-DMA: X panel rows 8i .. 8i + 7 per 1 KB load, Y panel rows
+// 256 / YW per 1 KB load (YW = NPMAX floats per Y row); Y columns at or past
+// npad read zeros.
+template <int NPMAX, int NW>
+__device__ __forceinline__ void panel_load(__amdgpu_buffer_rsrc_t rX, __amdgpu_buffer_rsrc_t rY,
+                                           int npad, int kt, float *st, int wave) {
+    constexpr int YW = NPMAX;
+    constexpr int RPL = 256 / YW;  // Y rows per load
+    constexpr int LPR = YW / 4;    // lanes per Y row
+    constexpr unsigned OUT = 0x80000000u;
+    const int lane = threadIdx.x & 63;
+    const int xrow = lane >> 3, xpos = lane & 7;
+    for (int i = wave; i < npad / 8; i += NW) {
+        const int row = 8 * i + xrow;
+        const int c = xpos ^ ((row >> 1) & 7);
+        const unsigned off = (unsigned)((row * npad + 32 * kt + 4 * c) * 4);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rX, (lds_void_t *)(st + i * 256), 16, off, 0, 0, 0);
+    }
+    float *ys = st + NPMAX * 32;
+#pragma unroll
+    for (int m = wave; m < 32 / RPL; m += NW) {
+        const int k = m * RPL + lane / LPR;
+        const int col = (4 * (lane % LPR)) ^ (32 * ((k >> 4) & 1));
+        const unsigned off = col < npad ? (unsigned)(((32 * kt + k) * npad + col) * 4) : OUT;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rY, (lds_void_t *)(ys + m * 256), 16, off, 0, 0, 0);
+    }
+}
+
+// Operands of one q step of a K panel: the left operand's 16-byte reads of
+// the wave's CNT blocks and the right operand's values of its two block
+// columns (the second one a copy of the first when all blocks share one).
+template <int CNT>
+struct PanelOps {
+    f4 a[CNT > 0 ? CNT : 1];
+    float b0[4], b1[4];
+};
+
+template <int NPMAX, int CNT, int MB>
+__device__ __forceinline__ void panel_ops(PanelOps<CNT> &o, const float *st, const int (&bi)[MB],
+                                          int col0, int col1, int q) {
+    constexpr int YW = NPMAX;
+    const int lane = threadIdx.x & 63;
     const int h = lane >> 5, l32 = lane & 31;
+    const float *ys = st + NPMAX * 32;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = 16 * h + 4 * q + t;
+        o.b0[t] = ys[k * YW + col0];
+        o.b1[t] = ys[k * YW + col1];
+    }
+#pragma unroll
+    for (int j = 0; j < CNT; ++j) {
+        const int row = bi[j] * 32 + l32;
+        o.a[j] = *(const f4 *)(st + row * 32 + 4 * ((4 * h + q) ^ ((row >> 1) & 7)));
+    }
+}
+
+// The MFMAs of one K panel for a wave that owns CNT blocks: blocks j < js
+// lie in block column c0, the rest in c0 + 1; bi[j] are their block rows.
+// The q steps are unrolled over two operand sets, so the reads of step
+// q + 1 are in flight while the MFMAs of step q run.
+template <int NPMAX, int CNT, int MB>
+__device__ __forceinline__ void panel_mfma(v16f (&acc)[MB], const float *st, const int (&bi)[MB],
+                                           int c0, int js) {
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int col0 = (c0 * 32 + l32) ^ (32 * h);
+    const int col1 = js < CNT ? ((c0 + 1) * 32 + l32) ^ (32 * h) : col0;
+    PanelOps<CNT> ops[2];
+    panel_ops<NPMAX, CNT, MB>(ops[0], st, bi, col0, col1, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < 3) panel_ops<NPMAX, CNT, MB>(ops[(q + 1) & 1], st, bi, col0, col1, q + 1);
+        const PanelOps<CNT> &o = ops[q & 1];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < CNT; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a[j][t], j < js ? o.b0[t] : o.b1[t],
+                                                              acc[j], 0, 0, 0);
+    }
+}
+
+// One product of the panel form, acc = X Y (X, Y npad x npad in memory,
+// zero padded), for a wave with CNT blocks.  Ends with a workgroup barrier
+// after the last panel.
+template <int NPMAX, int NW, int CNT, int MB>
+__device__ __forceinline__ void panel_product(v16f (&acc)[MB], const int (&bi)[MB], int c0, int js,
+                                              int npad, const float *X, const float *Y, float *L0,
+                                              float *L1, int wave) {
     const int nb = npad / 32;
     const int bytes = npad * npad * 4;
     const __amdgpu_buffer_rsrc_t rX =
         __builtin_amdgcn_make_buffer_rsrc((void *)X, (short)0, bytes, 0x00020000);
     const __amdgpu_buffer_rsrc_t rY =
         __builtin_amdgcn_make_buffer_rsrc((void *)Y, (short)0, bytes, 0x00020000);
-    constexpr unsigned OUT = 0x80000000u;  // beyond the buffer: reads zeros
-
-    // K panel kt into stage st: X panel rows 8i .. 8i + 7 per 1 KB load
-    // (i = wave, wave + 8, ...), Y panel row k per 1 KB load (k = wave + 8m).
-    const int xrow = lane >> 3;          // row within a 1 KB X load
-    const int xpos = lane & 7;           // chunk position within the row
-    auto load_panel = [&](int kt, float *st) {
-        for (int i = wave; i < npad / 8; i += WG_NW) {
-            const int row = 8 * i + xrow;
-            const int c = xpos ^ ((row >> 1) & 7);
-            const unsigned off = (unsigned)((row * npad + 32 * kt + 4 * c) * 4);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rX, (lds_void_t *)(st + i * 256), 16, off, 0,
-                                                     0, 0);
-        }
-        float *ys = st + 256 * 32;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int k = wave + WG_NW * m;
-            const int col = (4 * lane) ^ (32 * ((k >> 4) & 1));
-            const unsigned off =
-                col < npad ? (unsigned)(((32 * kt + k) * npad + col) * 4) : OUT;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rY, (lds_void_t *)(ys + k * 256), 16, off, 0,
-                                                     0, 0);
-        }
-    };
-
 #pragma unroll
     for (int j = 0; j < MB; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
-
-    auto body = [&](int kt, const float *st, float *nx) {
-        if (kt + 1 < nb) load_panel(kt + 1, nx);
-        const float *ys = st + 256 * 32;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            f4 a[MB];
-            float bv[MB][4];
-#pragma unroll
-            for (int j = 0; j < MB; ++j) {
-                if (j < b.cnt) {
-                    const int row = b.bi[j] * 32 + l32;
-                    a[j] = *(const f4 *)(st + row * 32 + 4 * ((4 * h + q) ^ ((row >> 1) & 7)));
-                    const int col = (b.bj[j] * 32 + l32) ^ (32 * h);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) bv[j][t] = ys[(16 * h + 4 * q + t) * 256 + col];
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int j = 0; j < MB; ++j)
-                    if (j < b.cnt)
-                        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j][t], bv[j][t], acc[j], 0,
-                                                                      0, 0);
-        }
-        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the next panel is in LDS
-        __syncthreads();
-    };
-    load_panel(0, L0);
-    __builtin_amdgcn_s_waitcnt(0x0f70);
+    panel_load<NPMAX, NW>(rX, rY, npad, 0, L0, wave);
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the panel is in LDS
     __syncthreads();
     for (int kt = 0; kt < nb; kt += 2) {
-        body(kt, L0, L1);
-        if (kt + 1 < nb) body(kt + 1, L1, L0);
+        if (kt + 1 < nb) panel_load<NPMAX, NW>(rX, rY, npad, kt + 1, L1, wave);
+        panel_mfma<NPMAX, CNT, MB>(acc, L0, bi, c0, js);
+        __builtin_amdgcn_s_waitcnt(0x0f70);
+        __syncthreads();
+        if (kt + 1 < nb) {
+            if (kt + 2 < nb) panel_load<NPMAX, NW>(rX, rY, npad, kt + 2, L0, wave);
+            panel_mfma<NPMAX, CNT, MB>(acc, L1, bi, c0, js);
+            __builtin_amdgcn_s_waitcnt(0x0f70);
+            __syncthreads();
+        }
     }
+}
+
+// The power's products for a wave with CNT blocks (CNT fixed, so the K
+// loop is fully unrolled over the blocks); see wg_power_panel.
+template <int NPMAX, int NW, int CNT, int MB>
+__device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t p, float *out,
+                                                 double *scale, float *SX, float *SAm, float *L0,
+                                                 float *L1, double *red, int eA, int t0, int wave) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+    const int npad = wg_npad(n), nb = npad / 32;
+    const int c0 = t0 / nb;
+    const int js = (c0 + 1) * nb - t0;  // blocks in column c0
+    int bi[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) bi[j] = j < js ? t0 - c0 * nb + j : j - js;
+    auto bcol = [&](int j) { return j < js ? c0 : c0 + 1; };
+
+    const int top = 63 - __clzll((unsigned long long)p);
+    int eX = eA;
+    double s = 0.0, S = 0.0;
+    bool first = true;
+    v16f acc[MB];
+    for (int bit = top - 1; bit >= 0; --bit) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool mul = pass == 1;
+            if (mul && !((p >> bit) & 1)) break;
+            const bool last = bit == 0 && (mul || !(p & 1));
+            const float *left = first ? SAm : SX;
+            panel_product<NPMAX, NW, CNT, MB>(acc, bi, c0, js, npad, left, mul ? SAm : left, L0,
+                                              L1, wave);
+            first = false;
+            double ss = 0.0;
+#pragma unroll
+            for (int j = 0; j < CNT; ++j) ss += block_sumsq(acc[j], bi[j], bcol(j), n);
+            S = wg_sum<NW>(ss, red);
+            s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
+            eX = exponent_of_sumsq(S);
+            if (last) break;
+            // C * 2^-e over the running matrix (its padding stays zero):
+            // buffer stores with one offset register per block and the row
+            // offsets in scalar registers
+            const PowScale f = pow2_neg(eX);
+            const __amdgpu_buffer_rsrc_t rS =
+                __builtin_amdgcn_make_buffer_rsrc((void *)SX, (short)0, npad * npad * 4, 0x00020000);
+#pragma unroll
+            for (int j = 0; j < CNT; ++j) {
+                const int vo = ((bi[j] * 32 + 4 * h) * npad + bcol(j) * 32 + l32) * 4;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int so = (8 * (r >> 2) + (r & 3)) * npad * 4;
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __builtin_bit_cast(unsigned, acc[j][r] * f.a * f.b), rS, vo, so, 0);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // stores done before the next product reads
+            __syncthreads();
+        }
+    }
+    double sc = s;
+    sc = sc > 4000.0 ? 4000.0 : (sc < -4000.0 ? -4000.0 : sc);
+    const PowScale f = pow2_neg(eX);
+#pragma unroll
+    for (int j = 0; j < CNT; ++j)
+        block_write_out(acc[j], bi[j], bcol(j), n, out, scale != nullptr, f, (int)sc);
+    if (scale && threadIdx.x == 0) *scale = (S == 0.0) ? 0.0 : s + (double)eX;
 }
 
 }  // namespace wgdetail
 
-// Sum of squares (float64) of an n x n matrix by the workgroup, fixed order;
-// every thread gets it.  Contains barriers.
-__device__ __forceinline__ double wg_matrix_sumsq(const float *__restrict__ M, int n, double *red) {
-    const int64_t total = (int64_t)n * n;
-    double acc = 0.0;
-    constexpr int U = 8;
-    for (int64_t b = threadIdx.x; b < total; b += WG_NT * U) {
-        float v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = b + (int64_t)u * WG_NT;
-            v[u] = i < total ? M[i] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc += (double)v[u] * (double)v[u];
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-#pragma unroll
-    for (int s = WG_NT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double S = red[0];
-    __syncthreads();
-    return S;
-}
-
-// A^p of one n x n matrix (1 <= n <= WG_MAX_N, or <= WG_RES_MAX_N when
-// RESIDENT_ONLY) by the calling workgroup of WG_NT threads, all of which
-// must call it.  LDS: L0 and L1 (WG_STAGE floats each; two distinct arrays,
-// so the compiler sees that loads into one do not alias reads from the
-// other) and `red` (WG_NT doubles).  `scratch` (panel path only,
-// n > WG_RES_MAX_N) holds 2 * wg_npad(n)^2 floats of this workgroup's own
-// memory.  out may be A.  Contains barriers; returns with the workgroup
-// synchronised.
-template <bool RESIDENT_ONLY>
-__device__ void wg_power(const float *A, int n, int64_t p, float *out, double *scale,
-                         float *scratch, float *L0, float *L1, double *red) {
+// A^p of one n x n matrix, 1 <= n <= NPMAX (64, 128 or 256), by the calling
+// workgroup of NW = 8 or 16 waves, all of which must call it.  L0 and L1 hold
+// WgPanelLds<NPMAX>::STAGE floats each (two distinct arrays), `red` NW
+// doubles; `scratch` holds 2 * wg_npad(n)^2 floats of this workgroup's own
+// memory, 16-byte aligned.  out may be A.  Contains barriers; returns with
+// the workgroup synchronised.
+template <int NPMAX, int NW>
+__device__ __forceinline__ void wg_power_panel(const float *A, int n, int64_t p, float *out, double *scale,
+                               float *scratch, float *L0, float *L1, double *red) {
     using namespace wgdetail;
+    static_assert(NW == 8 || NW == 16, "block ranges are cut for 8 or 16 waves");
+    static_assert(NPMAX == 64 || NPMAX == 128 || NPMAX == 256, "panel widths");
+    constexpr int NT = NW * 64;
+    constexpr int MB = (NPMAX / 32) * (NPMAX / 32) / NW > 0 ? (NPMAX / 32) * (NPMAX / 32) / NW : 1;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t total = (int64_t)n * n;
-
-    if (p == 0) {
-        for (int64_t i = tid; i < total; i += WG_NT) {
-            const int64_t r = i / n, c = i - r * n;
-            out[i] = (r == c) ? 1.0f : 0.0f;
-        }
-        if (scale && tid == 0) *scale = 0.0;
-        __syncthreads();
-        return;
-    }
-    const double SA = wg_matrix_sumsq(A, n, red);
-    const int eA = exponent_of_sumsq(SA);
-    if (p == 1) {
-        // out = A (unscaled) or A * 2^-eA with scale eA; each element is read
-        // and written by the same thread, so out may be A
-        const PowScale f = pow2_neg(eA);
-        for (int64_t i = tid; i < total; i += WG_NT) out[i] = scale ? A[i] * f.a * f.b : A[i];
-        if (scale && tid == 0) *scale = (SA == 0.0) ? 0.0 : (double)eA;
-        __syncthreads();
-        return;
-    }
+    double SA;
+    int eA;
+    if (!power_head<NT>(A, n, p, out, scale, red, &SA, &eA)) return;
 
     const int npad = wg_npad(n), nb = npad / 32;
-    const bool resident = RESIDENT_ONLY || n <= WG_RES_MAX_N;
-    const Blocks b = wave_blocks(nb, wave);
-    const PowScale fa = pow2_neg(eA);
-    // the normalised base: resident in L1 (as a 128-stride swizzled matrix)
-    // or in scratch (stride npad); zero padded to npad in both
     float *SX = scratch, *SAm = scratch + (size_t)npad * npad;
-    if (resident) {
-        for (int i = tid; i < npad * npad; i += WG_NT) {
-            const int r = i / npad, c = i - r * npad;
-            L1[res_idx(r, c)] = (r < n && c < n) ? A[(int64_t)r * n + c] * fa.a * fa.b : 0.f;
-        }
-    } else {
-        for (int i = tid; i < npad * npad; i += WG_NT) {
-            const int r = i / npad, c = i - r * npad;
-            SAm[i] = (r < n && c < n) ? A[(int64_t)r * n + c] * fa.a * fa.b : 0.f;
-        }
-        __builtin_amdgcn_s_waitcnt(0x0f70);
-    }
+    const PowScale fa = pow2_neg(eA);
+    copy_base_padded<NT>(A, n, npad, fa, [&](int r, int c, f4 v) {
+        *(f4 *)(SAm + r * npad + c) = v;
+    });
+    __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
 
-    const int top = 63 - __clzll((unsigned long long)p);
-    int eX = eA;
-    double s = 0.0;
-    bool first = true;
-    // RES: the resident path (at most 16 blocks, 2 per wave), else the panel
-    // path (at most 64 blocks, 8 per wave)
-    auto run = [&](auto res_tag) {
-        constexpr bool RES = decltype(res_tag)::value;
-        constexpr int MB = RES ? 2 : 8;
-        v16f acc[MB];
-        double S = 0.0;
-        for (int bit = top - 1; bit >= 0; --bit) {
-            for (int pass = 0; pass < 2; ++pass) {
-                const bool mul = pass == 1;
-                if (mul && !((p >> bit) & 1)) break;
-                const bool last = bit == 0 && (mul || !(p & 1));
-                if constexpr (RES) {
-                    const float *left = first ? L1 : L0;
-                    res_product<MB>(acc, b, nb, left, mul ? L1 : left);
-                } else {
-                    const float *left = first ? SAm : SX;
-                    panel_product<MB>(acc, b, npad, left, mul ? SAm : left, L0, L1);
-                }
-                first = false;
-                S = wg_block_sumsq<MB>(acc, b, n, red);  // barrier: X fully read
-                s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
-                eX = exponent_of_sumsq(S);
-                if (last) break;
-                // C * 2^-e over the running matrix (its padding stays zero)
-                const PowScale f = pow2_neg(eX);
-                const int lane = tid & 63, h = lane >> 5, l32 = lane & 31;
-#pragma unroll
-                for (int j = 0; j < MB; ++j) {
-                    if (j < b.cnt) {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int row = b.bi[j] * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                            const int col = b.bj[j] * 32 + l32;
-                            const float v = acc[j][r] * f.a * f.b;
-                            if constexpr (RES)
-                                L0[res_idx(row, col)] = v;
-                            else
-                                SX[row * npad + col] = v;
-                        }
-                    }
-                }
-                if constexpr (!RES) __builtin_amdgcn_s_waitcnt(0x0f70);  // stores done
-                __syncthreads();
-            }
-        }
-        wg_write_out<MB>(acc, b, n, out, scale, S, eX, s);
-    };
-    if (resident)
-        run(DmaBool<true>{});
-    else if constexpr (!RESIDENT_ONLY)
-        run(DmaBool<false>{});
-    __syncthreads();  // LDS and `red` may be reused by the caller
+    // this wave's range of the column-major block order
+    const int T = nb * nb;
+    const int rank = (NW / 4) * (wave & 3) + (wave >> 2);  // waves w, w + 4, ... share a SIMD
+    const int t0 = T * rank / NW, cnt = T * (rank + 1) / NW - t0;
+    // every wave takes part in the barriers of every product, whatever its count
+#define MPOW_PANEL_CASE(C)                                                                          \
+    case C:                                                                                         \
+        if constexpr (C <= MB)                                                                      \
+            panel_power_body<NPMAX, NW, C, (C < 1 ? 1 : C)>(A, n, p, out, scale, SX, SAm, L0, L1,   \
+                                                            red, eA, t0, wave);                     \
+        break;
+    switch (cnt) {
+        MPOW_PANEL_CASE(0)
+        MPOW_PANEL_CASE(1)
+        MPOW_PANEL_CASE(2)
+        MPOW_PANEL_CASE(3)
+        MPOW_PANEL_CASE(4)
+        MPOW_PANEL_CASE(5)
+        MPOW_PANEL_CASE(6)
+        MPOW_PANEL_CASE(7)
+        MPOW_PANEL_CASE(8)
+        default: break;
+    }
+#undef MPOW_PANEL_CASE
+    __syncthreads();  // LDS, scratch and `red` may be reused by the caller
 }
 
 }  // namespace mpow

@@ -401,7 +401,20 @@ hipError_t run_fp32_window(const Workspace &ws, const float *A, int n, const uin
 hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, float *out,
                          double *log2_scale, hipStream_t s, TimingSink *timing) {
     if (p == 0) return launch_identity(out, n, log2_scale, s);
-    if (ws.mode == MPOW_FP32 && !ws.escaleY && n <= kPowerWgMaxN &&
+    // a window schedule (plans that hold one), when it takes fewer products
+    // than binary
+    int bw = 1;
+    if (ws.mode == MPOW_FP32 && ws.escaleY && p >= 2) {
+        int best = mpow_gemm_count(p), result = 0;
+        for (int w = 2; w <= 3; ++w) {
+            const int gw = window_schedule(p, w, nullptr, 0, &result);
+            if (gw >= 0 && gw < best) {
+                best = gw;
+                bw = w;
+            }
+        }
+    }
+    if (ws.mode == MPOW_FP32 && bw == 1 && n <= kPowerWgMaxN &&
         (ws.kernel == MPOW_KERNEL_POWER_WG || (ws.kernel < 0 && n <= kPowerWgAutoMaxN))) {
         // the whole power in one workgroup, operands resident in LDS
         uint8_t ops[MPOW_MAX_STEPS];
@@ -418,22 +431,11 @@ hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, 
     const int G = schedule_of(p, ops);
     if (G == 0) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     if (ws.mode != MPOW_FP32) return run_split(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
-    if (ws.escaleY) {
-        // a window schedule, when it takes fewer products than binary
+    if (bw > 1) {
         uint8_t wops[3 * kMaxGraphOps];
-        int best = G, bw = 1, result = 0;
-        for (int w = 2; w <= 3; ++w) {
-            const int gw = window_schedule(p, w, nullptr, 0, &result);
-            if (gw >= 0 && gw < best) {
-                best = gw;
-                bw = w;
-            }
-        }
-        if (bw > 1) {
-            const int gw = window_schedule(p, bw, wops, kMaxGraphOps, &result);
-            if (gw > 0)
-                return run_fp32_window(ws, A, n, wops, gw, result, nbA, out, log2_scale, s, timing);
-        }
+        int result = 0;
+        const int gw = window_schedule(p, bw, wops, kMaxGraphOps, &result);
+        if (gw > 0) return run_fp32_window(ws, A, n, wops, gw, result, nbA, out, log2_scale, s, timing);
     }
     return run_fp32(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
 }
@@ -530,6 +532,7 @@ void batch_context_release(BatchContext *bc) {
         if (sl.host) (void)hipHostFree(sl.host);
     }
     if (bc->capture_stream) (void)hipStreamDestroy(bc->capture_stream);
+
     *bc = BatchContext();
 }
 
@@ -544,13 +547,28 @@ hipError_t batch_wait_all(BatchContext *bc) {
 }
 
 int batch_instance(int need, bool all_vec) {
-    // need 3: a matrix of the batch takes the whole-power workgroup instance,
-    // which then runs every matrix of the batch
-    if (need == 3) return 4;
     // the LDS-DMA instance replaces the 128x128 + 64x64 one when every matrix
     // allows 16-byte loads
     return (need == 1 && all_vec) ? 3 : need;
 }
+
+int batch_scratch_workers(const int workers[kBatchInstances]) {
+    int w = 0;
+    for (int i = 0; i < kBatchInstances; ++i)
+        if (batched_uses_scratch(i) && workers[i] > w) w = workers[i];
+    return w;
+}
+
+// Launch group of a matrix and the instance each group runs on: group 0 the
+// tiled shapes (on the smallest tiled instance that holds them all), 1 the
+// resident form at n <= 64 (instance 4), 2 the resident form at n <= 128
+// (5), 3 streamed panels at n > 128 (6), 4 streamed panels at n <= 128 (7).
+static int batch_group_of(int cfg, int n) {
+    if (cfg == 3) return n <= 64 ? 1 : (n <= 128 ? 2 : 3);
+    if (cfg == 4) return n <= 128 ? 4 : 3;
+    return 0;
+}
+constexpr int kGroupInst[kBatchGroups] = {-1, 4, 5, 6, 7};
 
 hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, const int *n,
                          const int64_t *p, float *const *out, double *const *scale,
@@ -561,23 +579,34 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         MPOW_TRY(hipEventSynchronize(sl.done));
         sl.pending = false;
     }
-    // Longest work first: estimated work (G(p) + 1) n^3, ties by input order.
-    std::vector<int> order(count);
+    // Matrices are grouped by the kernel instance that runs them (one launch
+    // per group) and, within a group, taken longest work first: estimated
+    // work (G(p) + 1) n^3, ties by input order.
+    std::vector<int> order(count), grp(count);
     std::vector<double> work(count);
     uint8_t ops[MPOW_MAX_STEPS];
+    int need = 0;  // the smallest tiled instance that holds every tiled matrix's shape
+    bool all_vec = true;
     for (int i = 0; i < count; ++i) {
         order[i] = i;
         const double nn = (double)n[i];
         work[i] = (double)(schedule_of(p[i], ops) + 1) * nn * nn * nn;
+        const int c = bc->cfg[(n[i] + 15) / 16];
+        grp[i] = batch_group_of(c, n[i]);
+        if (grp[i] == 0) {
+            const int nk = c == 2 ? 2 : (c == 0 ? 1 : 0);
+            need = nk > need ? nk : need;
+            all_vec = all_vec && n[i] % 4 == 0 && ((uintptr_t)A[i] & 15) == 0;
+        }
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return grp[a] != grp[b] ? grp[a] < grp[b] : work[a] > work[b];
+    });
     BatchHeader *hdr = (BatchHeader *)sl.host;
-    hdr->counter = 0;
+    *hdr = BatchHeader();
     hdr->count = count;
-    hdr->pad[0] = hdr->pad[1] = 0;
     BatchItem *items = (BatchItem *)(hdr + 1);
-    int need = 0;  // the smallest kernel instance that holds every matrix's tile
-    bool all_vec = true;
+    for (int g = 0; g < kBatchGroups; ++g) hdr->begin[g] = hdr->end[g] = 0;
     for (int k = 0; k < count; ++k) {
         const int i = order[k];
         items[k].A = A[i];
@@ -586,13 +615,21 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
         items[k].p = p[i];
         items[k].n = n[i];
         items[k].cfg = bc->cfg[(n[i] + 15) / 16];
-        const int c = items[k].cfg;
-        const int nk = c == 3 ? 3 : (c == 2 ? 2 : (c == 0 ? 1 : 0));
-        need = nk > need ? nk : need;
-        all_vec = all_vec && n[i] % 4 == 0 && ((uintptr_t)A[i] & 15) == 0;
+        const int g = grp[i];
+        if (hdr->end[g] == hdr->begin[g]) hdr->begin[g] = k;
+        hdr->end[g] = k + 1;
     }
-    const int inst = batch_instance(need, all_vec);
-    const int grid = bc->workers[inst];
+    double gwork[kBatchGroups] = {};
+    for (int i = 0; i < count; ++i) gwork[grp[i]] += work[i];
+    int inst[kBatchGroups];
+    for (int g = 0; g < kBatchGroups; ++g) {
+        if (hdr->end[g] == hdr->begin[g])
+            inst[g] = -1;
+        else if (g == 0)
+            inst[g] = batch_instance(need, all_vec);
+        else
+            inst[g] = kGroupInst[g];
+    }
     // Batches share the workers' scratch: order this one after the previous
     // one even when it was enqueued on another stream.
     if (bc->last >= 0 && bc->slot[bc->last].pending)
@@ -601,8 +638,25 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
     bl.desc = sl.desc;
     bl.scratch = bc->scratch;
     bl.slot_floats = bc->slot_floats;
+    // One persistent launch per group, in order on the stream, the group with
+    // the most estimated work first; each starts when the one before has
+    // drained (they share the workers' scratch).
+    int ord[kBatchGroups], ng = 0;
+    for (int g = 0; g < kBatchGroups; ++g)
+        if (inst[g] >= 0) ord[ng++] = g;
+    std::stable_sort(ord, ord + ng, [&](int a, int b) { return gwork[a] > gwork[b]; });
+    auto launch_all = [&](hipStream_t st) -> hipError_t {
+        for (int k = 0; k < ng; ++k) {
+            bl.group = ord[k];
+            const hipError_t e = launch_batched(bl, bc->workers[inst[ord[k]]], inst[ord[k]], st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    bool same = sl.graph_exec && sl.graph_count == count;
+    for (int g = 0; g < kBatchGroups; ++g) same = same && sl.graph_inst[g] == inst[g];
     if (use_graph) {
-        if (!sl.graph_exec || sl.graph_count != count || sl.graph_inst != inst) {
+        if (!same) {
             if (sl.graph_exec) {
                 (void)hipGraphExecDestroy(sl.graph_exec);
                 sl.graph_exec = nullptr;
@@ -611,7 +665,7 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
             MPOW_TRY(hipStreamBeginCapture(bc->capture_stream, hipStreamCaptureModeRelaxed));
             const hipError_t e1 = hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count),
                                                  hipMemcpyHostToDevice, bc->capture_stream);
-            const hipError_t e2 = launch_batched(bl, grid, inst, bc->capture_stream);
+            const hipError_t e2 = e1 == hipSuccess ? launch_all(bc->capture_stream) : hipSuccess;
             const hipError_t e3 = hipStreamEndCapture(bc->capture_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -624,12 +678,12 @@ hipError_t batch_enqueue(BatchContext *bc, int count, const float *const *A, con
                 return e4;
             }
             sl.graph_count = count;
-            sl.graph_inst = inst;
+            for (int g = 0; g < kBatchGroups; ++g) sl.graph_inst[g] = inst[g];
         }
         MPOW_TRY(hipGraphLaunch(sl.graph_exec, s));
     } else {
         MPOW_TRY(hipMemcpyAsync(sl.desc, sl.host, batch_desc_bytes(count), hipMemcpyHostToDevice, s));
-        MPOW_TRY(launch_batched(bl, grid, inst, s));
+        MPOW_TRY(launch_all(s));
     }
     MPOW_TRY(hipEventRecord(sl.done, s));
     sl.pending = true;

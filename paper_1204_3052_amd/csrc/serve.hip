@@ -245,8 +245,7 @@ mpow_status mpow_srv_create(mpow_srv_t *out_srv, int device, int max_n, size_t h
         const int bmax = max_n < kBatchMaxN ? max_n : kBatchMaxN;
         int workers[kBatchInstances] = {};
         const bool ok = batch_workers_for(device, workers);
-        int wmax = 0;
-        for (int w : workers) wmax = w > wmax ? w : wmax;
+        const int wmax = batch_scratch_workers(workers);
         if (!ok ||
             hipMalloc((void **)&srv->batch_dev, batch_device_bytes(max_batch, bmax, wmax)) != hipSuccess ||
             batch_context_init(&srv->batch, srv->batch_dev, max_batch, bmax, workers) != hipSuccess)

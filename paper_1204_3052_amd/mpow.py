@@ -246,15 +246,32 @@ def mpow_expm(plan: int, A: int, n: int, out: int, log2_scale: int | None, squar
     _check(st, "mpow_expm")
 
 
-def mpow_run_batched(plan: int, count: int, A_ptrs, ns, ps, out_ptrs, log2_scale: int | None,
-                     stream: int | None) -> None:
+class BatchArgs:
+    """The host arrays of one batch (input pointers, sizes, powers, output
+    pointers) marshalled once, for calling mpow_run_batched repeatedly on the
+    same matrices without rebuilding them."""
+
+    def __init__(self, A_ptrs, ns, ps, out_ptrs):
+        c = ctypes
+        self.count = count = len(ns)
+        if not (len(A_ptrs) == len(ps) == len(out_ptrs) == count):
+            raise ValueError("batch arrays differ in length")
+        self.a = (c.c_void_p * count)(*A_ptrs)
+        self.o = (c.c_void_p * count)(*out_ptrs)
+        self.n = (c.c_int * count)(*[int(x) for x in ns])
+        self.p = (c.c_int64 * count)(*[int(x) for x in ps])
+
+
+def mpow_run_batched(plan: int, count: int, A_ptrs, ns=None, ps=None, out_ptrs=None,
+                     log2_scale: int | None = None, stream: int | None = None) -> None:
+    """A_ptrs is either the list of input pointers (then ns, ps and out_ptrs
+    are the other lists) or a BatchArgs (ns, ps and out_ptrs unused)."""
     c = ctypes
-    a = (c.c_void_p * count)(*A_ptrs)
-    o = (c.c_void_p * count)(*out_ptrs)
-    nn = (c.c_int * count)(*[int(x) for x in ns])
-    pp = (c.c_int64 * count)(*[int(x) for x in ps])
-    st = _load().mpow_run_batched(plan, int(count), c.cast(a, c.c_void_p), c.cast(nn, c.c_void_p),
-                                  c.cast(pp, c.c_void_p), c.cast(o, c.c_void_p),
+    b = A_ptrs if isinstance(A_ptrs, BatchArgs) else BatchArgs(A_ptrs, ns, ps, out_ptrs)
+    if count > b.count:
+        raise ValueError("count exceeds the batch arrays")
+    st = _load().mpow_run_batched(plan, int(count), c.cast(b.a, c.c_void_p), c.cast(b.n, c.c_void_p),
+                                  c.cast(b.p, c.c_void_p), c.cast(b.o, c.c_void_p),
                                   log2_scale or None, stream or None)
     _check(st, "mpow_run_batched")
 

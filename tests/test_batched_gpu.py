@@ -256,11 +256,11 @@ def test_tile_shapes_bit_identical(plans):
     results = []
     # all 128x128, all 64x64 (the instance without the large tile), a mix of
     # both in one launch, all 256x256 (the 8-wave instance), a mix of those,
-    # the whole-power workgroup instance, and a mix including it
-    tables = [[0] * mpow.TILE_TABLE_LEN, [1] * mpow.TILE_TABLE_LEN,
-              [b % 2 for b in range(mpow.TILE_TABLE_LEN)], [2] * mpow.TILE_TABLE_LEN,
-              [b % 3 for b in range(mpow.TILE_TABLE_LEN)], [3] * mpow.TILE_TABLE_LEN,
-              [b % 4 for b in range(mpow.TILE_TABLE_LEN)]]
+    # the whole power per workgroup (resident, then streamed panels), and
+    # mixes of every shape (several launch groups in one batch)
+    L = mpow.TILE_TABLE_LEN
+    tables = [[0] * L, [1] * L, [b % 2 for b in range(L)], [2] * L, [b % 3 for b in range(L)],
+              [3] * L, [4] * L, [b % 5 for b in range(L)], [(b + 3) % 5 for b in range(L)]]
     for table in tables:
         mpow.mpow_plan_tile_table(hb, table)
         pk.out.fill_(float("nan"))
@@ -279,7 +279,7 @@ def test_autotune_and_cache(plans, tmp_path):
     print("  [gpu] mpow_plan_autotune", flush=True)
     mpow.mpow_plan_autotune(hb, cache, mpow.MPOW_TUNE_FORCE)
     table = mpow.mpow_plan_tile_table(hb)
-    assert all(0 <= t < 2 for t in table)
+    assert all(0 <= t < 5 for t in table)
     text = open(cache).read().splitlines()
     assert text[0].startswith("mpow-tune ") and len(text) == 17
     h2 = mpow.mpow_plan_create(0, 256, 16, mpow.MPOW_FP32, 0)
@@ -289,17 +289,19 @@ def test_autotune_and_cache(plans, tmp_path):
         assert mpow.mpow_plan_tile_table(h2)[1:] == table[1:]
     finally:
         mpow.mpow_plan_destroy(h2)
-    for bad in (4, 7, -1):
+    for bad in (5, 7, -1):
         with pytest.raises(mpow.MpowError):
             mpow.mpow_plan_tile_table(hb, [bad] * mpow.TILE_TABLE_LEN)
 
 
-def test_whole_power_instance_equals_plain_bitwise(plans):
-    # the whole-power workgroup instance (tile shape 3) on ragged sizes of
-    # any alignment, and on multiple-of-4 sizes with 2^+-70-scaled inputs
+@pytest.mark.parametrize("shape", [3, 4])
+def test_whole_power_instance_equals_plain_bitwise(plans, shape):
+    # the whole power per workgroup (tile shape 3: operands resident in LDS
+    # up to n = 128; shape 4: streamed panels) on ragged sizes of any
+    # alignment, and on multiple-of-4 sizes with 2^+-70-scaled inputs
     hb, hp = plans
     saved = mpow.mpow_plan_tile_table(hb)
-    mpow.mpow_plan_tile_table(hb, [3] * mpow.TILE_TABLE_LEN)
+    mpow.mpow_plan_tile_table(hb, [shape] * mpow.TILE_TABLE_LEN)
     try:
         for mats, ps in (edge_batch(6), edge4_batch(7)):
             pk = Packed(mats)
@@ -315,5 +317,34 @@ def test_whole_power_instance_equals_plain_bitwise(plans):
                     ob, _ = pk.result(i)
                     op, _ = run_gpu(hp, A, p, log_scale=False)
                     assert np.array_equal(ob, op), (A.shape[0], p)
+    finally:
+        mpow.mpow_plan_tile_table(hb, saved)
+
+
+def test_back_to_back_batches_with_launch_groups(plans):
+    # Several batches in flight on one stream (no synchronisation between the
+    # calls, so descriptor slots and workers' scratch are reused while earlier
+    # batches run), with a table that splits each batch into several launch
+    # groups: every call's results equal those of a synchronised call.
+    import torch
+    hb, _ = plans
+    mats, ps = edge_batch(11)
+    saved = mpow.mpow_plan_tile_table(hb)
+    try:
+        mpow.mpow_plan_tile_table(hb, [(b + 1) % 5 for b in range(mpow.TILE_TABLE_LEN)])
+        ref = Packed(mats)
+        run_batch(hb, ref, ps)
+        want = [ref.result(i) for i in range(len(ps))]
+        packs = [Packed(mats) for _ in range(4)]
+        st = torch.cuda.current_stream().cuda_stream
+        print(f"  [gpu] {len(packs)} back-to-back batches of {len(ps)}", flush=True)
+        for pk in packs:
+            mpow.mpow_run_batched(hb, len(ps), mpow.BatchArgs(pk.a_ptrs, pk.ns, ps, pk.o_ptrs),
+                                  log2_scale=pk.scale.data_ptr(), stream=st)
+        torch.cuda.synchronize()
+        for pk in packs:
+            for i in range(len(ps)):
+                M, s = pk.result(i)
+                assert np.array_equal(M, want[i][0]) and s == want[i][1], i
     finally:
         mpow.mpow_plan_tile_table(hb, saved)
