@@ -230,6 +230,8 @@ def batched_workload(args):
     torch.cuda.set_device(dev)
     count = 4096
     ns, ps = inputs.ragged_batch(count, 3)
+    if args.batch_n > 0:  # every matrix of one size, the same powers
+        ns = [args.batch_n] * count
     offs, o = [], 0
     for n in ns:
         offs.append(o)
@@ -248,7 +250,10 @@ def batched_workload(args):
     hp = mpow.mpow_plan_create(0, 256, 0, mpow.MPOW_FP32, 0)
     default_table = mpow.mpow_plan_tile_table(hb)
     t0 = time.perf_counter()
-    mpow.mpow_plan_autotune(hb, None, mpow.MPOW_TUNE_FORCE)
+    if args.tile_shape >= 0:  # one fixed tile shape for every size, no tuning
+        mpow.mpow_plan_tile_table(hb, [args.tile_shape] * mpow.TILE_TABLE_LEN)
+    elif args.tile_shape == -1:
+        mpow.mpow_plan_autotune(hb, None, mpow.MPOW_TUNE_FORCE)
     tune_s = time.perf_counter() - t0
     tuned_table = mpow.mpow_plan_tile_table(hb)
     nl, pl = [int(x) for x in ns], [int(x) for x in ps]
@@ -274,7 +279,10 @@ def batched_workload(args):
     # host prepares each batch while the previous ones run, as a serving loop
     # would), ms per batch = elapsed / K.  The loop of plain calls is timed
     # the same way, one pass per step.
-    for name, fn in (("batched", batched), ("batched_untuned", batched_default), ("loop_plain", looped)):
+    legs = [("batched", batched), ("batched_untuned", batched_default), ("loop_plain", looped)]
+    if args.tile_shape != -1 or args.batch_n > 0:
+        legs = legs[:1]
+    for name, fn in legs:
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize(dev)
@@ -314,7 +322,11 @@ def batched_workload(args):
               "effective_gflop_per_batch": round(flop / 1e9, 2), "results": res,
               "tile_table": {"tuned": tuned_table[1:], "default": default_table[1:],
                              "tune_seconds": round(tune_s, 2)},
-              "speedup_vs_loop": round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)}
+              "speedup_vs_loop": (round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)
+                                  if "loop_plain" in res else None)}
+    if args.batch_n > 0:
+        result["workload"] = (f"uniform batch: 4096 FP32 matrices of n = {args.batch_n}, "
+                              "p log-uniform [2,1000]")
     if not args.no_cpu_baseline:
         cpu, errs = sample_oracle_leg({i: (A, p, 0, M, s) for i, (A, p, M, s) in kept.items()})
         result["sample_errors"] = errs
@@ -820,6 +832,49 @@ def stochastic_oracle_check(res, kept):
     res["row_sum_dev"] = float(f"{np.max(np.abs(oracle.to_value(M, s).sum(axis=1) - 1.0)):.3e}")
 
 
+def vendor16_workload(args):
+    """Context for the 16-bit products: a plain BF16 8192^3 GEMM from the
+    vendor library (torch.matmul, four calls back to back) next to one BF16X3
+    power A^5 at N = 8192 on the 256 x 256 split tile (three products), each
+    launch timed by HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_1204_3052_amd import inputs, mpow
+
+    n = 8192
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    g = torch.Generator(device=dev).manual_seed(0)
+    a = torch.randn(n, n, dtype=torch.bfloat16, device=dev, generator=g)
+    b = torch.randn(n, n, dtype=torch.bfloat16, device=dev, generator=g)
+    lib_ms = []
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        torch.matmul(a, b)
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        lib_ms.append(e0.elapsed_time(e1))
+    A = torch.from_numpy(inputs.gaussian(n, 1)).to(dev)
+    out = torch.empty_like(A)
+    h = mpow.mpow_plan_create(0, n, 0, mpow.MPOW_BF16X3, mpow.MPOW_FLAG_TIMING)
+    mpow.mpow_plan_set_kernel(h, mpow.MPOW_KERNEL_GEMM_BF16X3_256)
+    mpow.mpow_run(h, A.data_ptr(), n, 5, out.data_ptr(), None, stream.cuda_stream)
+    torch.cuda.synchronize(dev)
+    launches, ms, flop, name = mpow.mpow_plan_timing(h, mpow.MPOW_KERNEL_GEMM_BF16X3_256)
+    mpow.mpow_plan_destroy(h)
+    flop16 = 2.0 * n ** 3
+    print(json.dumps({
+        "workload": "BF16 8192^3: vendor GEMM (torch.matmul) x4, then a BF16X3 power A^5 (3 products)",
+        "vendor_gemm_ms": [round(x, 3) for x in lib_ms],
+        "vendor_gemm_pflops": [round(flop16 / x / 1e12, 3) for x in lib_ms],
+        "bf16x3_products": int(launches), "bf16x3_ms_per_product": round(ms / launches, 3),
+        "bf16x3_16bit_pflops": round(3 * flop / ms / 1e12, 3), "kernel": name}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -827,11 +882,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "split", "batched", "serving", "paper", "expm", "window"],
+                    choices=["plain", "split", "batched", "serving", "paper", "expm", "window", "vendor16"],
                     help="plain: the FP32 benchmark (default); split: FP32 vs FP16X3 vs BF16X3 "
                          "at N=4096, p in {64, 1000}, with errors against the oracle")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serving workload: seconds of Poisson arrivals")
+    ap.add_argument("--batch-n", type=int, default=0,
+                    help="batched workload: every matrix of this size instead of the ragged sizes")
+    ap.add_argument("--tile-shape", type=int, default=-1,
+                    help="batched workload: this tile shape (0-4) for every size instead of "
+                         "tuning; -2: the untuned default table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -865,6 +925,8 @@ def main():
         return expm_workload(args)
     if args.workload == "window":
         return window_workload(args)
+    if args.workload == "vendor16":
+        return vendor16_workload(args)
 
     import numpy as np
     import torch

@@ -272,22 +272,39 @@ mpow_status mpow_plan_tile_table(mpow_plan_t plan, int *table, int len, int set)
 
 #define MPOW_TUNE_FORCE 1u /* ignore an existing cache file */
 
-/* Autotuner (precedent: the per-problem tile choice of section 4.3.7): for
- * every size bucket up to min(max_n, 256) times each of the five tile shapes
- * of the batched kernel on a synthetic batch of that size that fills all
- * workers twice (p = 100, eight products), run through mpow_run_batched's
- * own grouping and launches.  Because a mixed batch runs one launch per
- * kernel instance it needs, one after another, whole tables are then timed
- * on a synthetic ragged batch (sizes uniform over the buckets, p
- * log-uniform in [2, 1000]): the per-bucket winners, the table before
- * tuning, and each single shape for all sizes; the fastest becomes the
- * plan's tile table.  If cache_path is non-NULL and holds
- * a table written for the same GPU model (architecture and CU count), that
- * table is loaded instead (unless MPOW_TUNE_FORCE); a fresh table is written
- * there.  Synchronous; allocates temporary device memory (not on the run
- * path).  Errors: INVALID (plan without batch support, unknown flags),
- * UNSUPPORTED (mode other than MPOW_FP32), NOMEM, DEVICE. */
+/* Autotuner (precedent: the per-problem tile choice of section 4.3.7).
+ * Every plan: for each 256-wide size bucket n = 256 b up to
+ * min(max_n, 8192) (from n = 768 for MPOW_FP32, whose smaller sizes keep the
+ * whole-K tile), times one product (a power A^2) on each product kernel of
+ * the plan's mode that adds the products in the per-size default's order
+ * (float32: the LDS-DMA 256x128, 256x256, 128x128 and 64x64 tiles; split
+ * modes: the 128x128 and 256x256 tiles) and keeps the fastest for sizes of
+ * that bucket, for 16-byte-loadable inputs (float32) or all inputs (split
+ * modes); results are bit for bit those of the default picks.
+ * MPOW_FP32 plans with batch support also tune the batched kernel's tile
+ * table: every size bucket up to min(max_n, 256) times each of the five tile
+ * shapes on a synthetic batch of that size that fills all workers twice
+ * (p = 100, eight products), run through mpow_run_batched's own grouping and
+ * launches; because a mixed batch runs one launch per kernel instance it
+ * needs, one after another, whole tables are then timed on a synthetic
+ * ragged batch (sizes uniform over the buckets, p log-uniform in [2, 1000]):
+ * the per-bucket winners, the table before tuning, and each single shape for
+ * all sizes; the fastest becomes the plan's tile table.
+ * If cache_path is non-NULL and holds choices written for the same GPU model
+ * (architecture and CU count) and mode that cover everything this plan tunes,
+ * they are loaded instead (unless MPOW_TUNE_FORCE); otherwise the fresh
+ * choices are written there.  Synchronous; allocates temporary device memory
+ * (not on the run path).  Errors: INVALID (plan NULL, unknown flags), NOMEM,
+ * DEVICE. */
 mpow_status mpow_plan_autotune(mpow_plan_t plan, const char *cache_path, uint32_t flags);
+
+/* The product kernel (an MPOW_KERNEL_* id) mpow_run on this plan uses at size
+ * n: the forced kernel, else the autotuned pick for n's size bucket, else the
+ * per-size default; MPOW_KERNEL_POWER_WG where the whole power runs in one
+ * workgroup (float32 plans without MPOW_FLAG_WINDOW; window plans report the
+ * product kernel of their window schedules).  aligned != 0: a 16-byte
+ * aligned input.  Host only.  -1 for a NULL plan or n outside 1..max_n. */
+int mpow_plan_kernel_for(mpow_plan_t plan, int n, int aligned);
 
 /* Forces the product kernel that mpow_run / mpow_run_naive use on this plan
  * for every n (kernel: an MPOW_KERNEL_* id of the plan's mode), or restores

@@ -68,7 +68,7 @@ hipError_t enqueue_expm(const Workspace &ws, float *T, const float *A, int n, in
     if (e != hipSuccess) return e;
 
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    int kernel = ws_product_kernel(ws, n, vec4);
     kernel = gemm_resolve(kernel, n, vec4);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
     const float *Y = ws.buf[0];

@@ -21,6 +21,10 @@ namespace mpow {
 //                   output (C_0 = A), written by the kernel that consumes C_k
 //  sx, sa           split modes: 16-bit hi/lo of the running matrix and of A
 //                   (row-major hi, lo, then transposed hi, lo), ld x ld each
+// Size buckets of the tuned product-kernel picks: n in (256 (b - 1), 256 b]
+// for b = 1 .. kPickBuckets - 1 (up to n = 8192).
+constexpr int kPickBuckets = 33;
+
 struct Workspace {
     float *buf[2] = {nullptr, nullptr};
     double *part[2] = {nullptr, nullptr};
@@ -37,6 +41,9 @@ struct Workspace {
     int max_n = 0;
     int mode = MPOW_FP32;
     int kernel = -1;  // product kernel forced for every size, -1: per-size default
+    // product kernel measured fastest by mpow_plan_autotune for n in
+    // (256 (b - 1), 256 b], stored as id + 1 (0: none, the per-size default)
+    int8_t pick1[kPickBuckets] = {};
     // window schedules (plans with MPOW_FLAG_WINDOW): A^2, A^3, A^5, A^7 with
     // their partial sums, and the right operand's exponent of every product
     float *wp[4] = {};
@@ -211,6 +218,10 @@ inline double tile_fill_rate(double rate, int n, int bm, int bn) {
     return rate * (T / 256.0) / waves;
 }
 int gemm_pick(int n, bool vec4);            // default kernel id for size n
+// The product kernel a power on workspace ws uses at size n: the forced
+// kernel, else the tuned pick for n's bucket, else the per-size default
+// (float32: gemm_pick, before gemm_resolve; split modes: gemm_split_pick).
+int ws_product_kernel(const Workspace &ws, int n, bool vec4);
 bool gemm_is_f32(int kernel);
 int gemm_tiles(int kernel, int n);          // number of tiles (= partials written)
 // The kernel id that runs for `kernel` at size n: the LDS-DMA kernels need

@@ -183,6 +183,18 @@ int window_schedule(int64_t p, int w, uint8_t *ops, int cap, int *result) {
     return k;
 }
 
+int ws_product_kernel(const Workspace &ws, int n, bool vec4) {
+    if (ws.kernel >= 0) return ws.kernel;
+    const int b = (n + 255) / 256;
+    if (ws.mode == MPOW_FP32) {
+        // tuned picks are among the LDS-DMA tiles (16-byte loads) from n = 768
+        if (vec4 && n >= 768 && b < kPickBuckets && ws.pick1[b] > 0) return ws.pick1[b] - 1;
+        return gemm_pick(n, vec4);
+    }
+    if (b < kPickBuckets && ws.pick1[b] > 0) return ws.pick1[b] - 1;
+    return gemm_split_pick(ws.mode, n);
+}
+
 namespace {
 
 int schedule_of(int64_t p, uint8_t *ops) {
@@ -208,7 +220,7 @@ hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const
                     int G, int nbA, float *out, double *log2_scale, hipStream_t s,
                     TimingSink *timing) {
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    int kernel = ws_product_kernel(ws, n, vec4);
     kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
@@ -303,7 +315,7 @@ hipError_t run_split(const Workspace &ws, const float *A, int n, int64_t p, cons
     const int mode = ws.mode;
     const int ld = split_ld(n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
-    const int kernel = ws.kernel >= 0 ? ws.kernel : gemm_split_pick(mode, n);
+    const int kernel = ws_product_kernel(ws, n, false);
     const int tiles = gemm_split_tiles(kernel, n);
 
     const int np = split_parts(mode);
@@ -358,7 +370,7 @@ hipError_t run_fp32_window(const Workspace &ws, const float *A, int n, const uin
                            int G, int result, int nbA, float *out, double *log2_scale,
                            hipStream_t s, TimingSink *timing) {
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    int kernel = ws_product_kernel(ws, n, vec4);
     kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
@@ -447,7 +459,7 @@ hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64
     MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
     if (p == 1) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
-    int kernel = ws.kernel >= 0 ? ws.kernel : gemm_pick(n, vec4);
+    int kernel = ws_product_kernel(ws, n, vec4);
     kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;

@@ -66,7 +66,8 @@ EXPORTS = (
     "mpow_plan_create", "mpow_plan_destroy", "mpow_run", "mpow_run_naive", "mpow_run_noalloc",
     "mpow_run_batched", "mpow_expm",
     "mpow_last_device_error", "mpow_plan_timing", "mpow_plan_timing_reset",
-    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_set_kernel", "mpow_fp32_kernel_for",
+    "mpow_plan_tile_table", "mpow_plan_autotune", "mpow_plan_kernel_for", "mpow_plan_set_kernel",
+    "mpow_fp32_kernel_for",
     "mpow_mode_for_tolerance",
     "mpow_srv_create", "mpow_srv_submit", "mpow_srv_poll", "mpow_srv_wait_idle", "mpow_srv_stats",
     "mpow_srv_destroy", "mpow_srv_simulate",
@@ -146,6 +147,7 @@ def _load():
         "mpow_plan_timing_reset": (c.c_int, [P]),
         "mpow_plan_tile_table": (c.c_int, [P, P, c.c_int, c.c_int]),
         "mpow_plan_autotune": (c.c_int, [P, c.c_char_p, c.c_uint32]),
+        "mpow_plan_kernel_for": (c.c_int, [P, c.c_int, c.c_int]),
         "mpow_plan_set_kernel": (c.c_int, [P, c.c_int]),
         "mpow_mode_for_tolerance": (c.c_int, [c.c_double, c.c_double, c.c_int]),
         "mpow_srv_create": (c.c_int, [c.POINTER(P), c.c_int, c.c_int, c.c_size_t, c.c_int, c.c_int, c.c_uint32]),
@@ -287,6 +289,11 @@ def mpow_plan_timing(plan: int, kernel: int):
     _check(_load().mpow_plan_timing(plan, int(kernel), c.byref(l), c.byref(m), c.byref(f), c.byref(nm)),
            "mpow_plan_timing")
     return l.value, m.value, f.value, (nm.value.decode() if nm.value else None)
+
+
+def mpow_plan_kernel_for(plan: int, n: int, aligned: bool = True) -> int:
+    """The product kernel id mpow_run on this plan uses at size n."""
+    return int(_load().mpow_plan_kernel_for(plan, int(n), 1 if aligned else 0))
 
 
 def mpow_plan_timing_reset(plan: int) -> None:
