@@ -494,7 +494,7 @@ def sample_oracle_leg(kept):
         errs.append({"n": n, "p": p, "mode": "bf16x3" if mode else "fp32", "rel_err": float(f"{err:.3e}"),
                      "tol": float(f"{tol:.3e}"), "within_tol": err <= tol})
     cpu = {"value": flop / spent / 1e9, "unit": "GFLOP/s", "cores": blas_threads(), "host_cores": host_cores(), "kind": "oracle",
-           "sample": f"FP64 oracle binary exponentiation on {len(kept)} sampled matrices; {spent:.1f} s"}
+           "sample": f"FP64 oracle binary exponentiation on {len(kept)} sampled matrices; {spent:.3f} s"}
     return cpu, errs
 
 

@@ -332,7 +332,9 @@ mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel);
  * kernel returned here is then the one of its naive and window forms. */
 int mpow_fp32_kernel_for(int n, int aligned);
 
-/* The last hipError_t value a call on this plan saw (0 if none). */
+/* The last hipError_t value a call on this plan saw (0 if none): the HIP
+ * error behind an MPOW_ERR_DEVICE status (the "last HIP error" query of this
+ * boundary; a server reports its own in mpow_srv_stats).  Host only. */
 int mpow_last_device_error(mpow_plan_t plan);
 
 /* Kernel identifiers for timing queries. */
