@@ -30,15 +30,15 @@
 //    workgroup's own scratch), and each product streams K panels of 32
 //    (n_pad x 32 of X, 32 x n_pad of Y) into two LDS stages by LDS-DMA
 //    buffer loads, the next panel loading while the current one feeds the
-//    MFMAs; each element of X and Y is read once per product.  The block
-//    grid in column-major order is cut into NW contiguous ranges of
-//    floor or ceil (nb^2 / NW) blocks (NW = 8 or 16 waves), range r going
-//    to the wave of rank r (the waves that share a SIMD hold consecutive
-//    ranges, so the SIMDs carry equal work): a wave's blocks then lie in at
-//    most two block columns, and it reads each right-operand value once for
-//    all of them.  For n <= 256 sixteen waves hold at most four blocks each
-//    (64 accumulator registers), which leaves registers to read the next
-//    step's operands while the MFMAs of the current one run.
+//    MFMAs; each element of X and Y is read once per product.  Each of the
+//    NW = 8 or 16 waves owns consecutive blocks of one block column, at
+//    most ceil(nb^2 / NW) of them, and the waves that share a SIMD own the
+//    balanced share ceil(nb^2 / 4) or less together (a fixed table per nb):
+//    a wave reads each right-operand value once for all its blocks, and
+//    every MFMA's operands are fixed at compile time.  For n <= 256 sixteen
+//    waves hold at most four blocks each (64 accumulator registers), which
+//    leaves registers to read the next step's operands while the MFMAs of
+//    the current one run.
 //    The number of blocks selects a fully unrolled instance of the K loop.
 //    Layouts as the LDS-DMA tiles: X panel chunk c of row r at
 //    c ^ ((r / 2) % 8), Y panel rows with bit 4 of k set swapping their
@@ -381,6 +381,56 @@ __device__ __forceinline__ void wg_power_resident(const float *A, int n, int64_t
 
 namespace wgdetail {
 
+// Which blocks each wave of the panel form owns, for nb = npad / 32 blocks
+// per side: entry [nb - 1][w] = c | r0 << 4 | cnt << 8 gives wave w block
+// rows r0 .. r0 + cnt - 1 of block column c.  Every wave's blocks lie in one
+// block column (its right-operand values serve all of them, and no MFMA
+// has to choose between two columns), no wave holds more than
+// ceil(nb^2 / NW) blocks, and the waves of each SIMD (w, w + 4, ...) hold
+// at most ceil(nb^2 / 4) blocks together, the balanced share; pieces_ok
+// checks all of this at compile time.  (A column cut into ceil(nb / m)
+// near-equal pieces of at most m = ceil(nb^2 / NW) blocks gives at most NW
+// pieces here; they were placed on the SIMDs by exhaustive search.)
+constexpr unsigned short kPieces16[8][16] = {
+    {0x100, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000},  // nb = 1
+    {0x100, 0x110, 0x101, 0x111, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000},  // nb = 2
+    {0x100, 0x101, 0x102, 0x000, 0x110, 0x111, 0x112, 0x000, 0x120, 0x121, 0x122, 0x000, 0x000, 0x000, 0x000, 0x000},  // nb = 3
+    {0x100, 0x101, 0x102, 0x103, 0x110, 0x111, 0x112, 0x113, 0x120, 0x121, 0x122, 0x123, 0x130, 0x131, 0x132, 0x133},  // nb = 4
+    {0x200, 0x221, 0x203, 0x224, 0x220, 0x202, 0x223, 0x143, 0x201, 0x222, 0x204, 0x144, 0x140, 0x141, 0x142, 0x000},  // nb = 5
+    {0x300, 0x331, 0x303, 0x334, 0x330, 0x302, 0x333, 0x305, 0x301, 0x332, 0x304, 0x335, 0x000, 0x000, 0x000, 0x000},  // nb = 6
+    {0x400, 0x403, 0x406, 0x343, 0x401, 0x404, 0x340, 0x344, 0x402, 0x405, 0x341, 0x345, 0x000, 0x000, 0x342, 0x346},  // nb = 7
+    {0x400, 0x402, 0x404, 0x406, 0x440, 0x442, 0x444, 0x446, 0x401, 0x403, 0x405, 0x407, 0x441, 0x443, 0x445, 0x447},  // nb = 8
+};
+constexpr unsigned short kPieces8[4][8] = {
+    {0x100, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000, 0x000},  // nb = 1
+    {0x100, 0x110, 0x101, 0x111, 0x000, 0x000, 0x000, 0x000},  // nb = 2
+    {0x200, 0x201, 0x202, 0x000, 0x120, 0x121, 0x122, 0x000},  // nb = 3
+    {0x200, 0x201, 0x202, 0x203, 0x220, 0x221, 0x222, 0x223},  // nb = 4
+};
+
+template <int NW, int NBMAX>
+constexpr bool pieces_ok(const unsigned short (&t)[NBMAX][NW]) {
+    for (int nb = 1; nb <= NBMAX; ++nb) {
+        int cover[16][16] = {};
+        int simd[4] = {};
+        const int m = (nb * nb + NW - 1) / NW, share = (nb * nb + 3) / 4;
+        for (int w = 0; w < NW; ++w) {
+            const int c = t[nb - 1][w] & 15, r0 = (t[nb - 1][w] >> 4) & 15, cnt = t[nb - 1][w] >> 8;
+            if (cnt > m || (cnt > 0 && (c >= nb || r0 + cnt > nb))) return false;
+            for (int r = r0; r < r0 + cnt; ++r) cover[r][c] += 1;
+            simd[w % 4] += cnt;
+        }
+        for (int i = 0; i < 4; ++i)
+            if (simd[i] > share) return false;
+        for (int r = 0; r < nb; ++r)
+            for (int c = 0; c < nb; ++c)
+                if (cover[r][c] != 1) return false;
+    }
+    return true;
+}
+static_assert(pieces_ok<16, 8>(kPieces16) && pieces_ok<8, 4>(kPieces8),
+              "every block owned once, by waves of balanced SIMDs");
+
 // K panel kt of X and Y (npad x npad in memory, row stride npad) into stage
 // `st` by LDS-DMA: X panel rows 8i .. 8i + 7 per 1 KB load, Y panel rows
 // 256 / YW per 1 KB load (YW = NPMAX floats per Y row); Y columns at or past
@@ -392,7 +442,14 @@ __device__ __forceinline__ void panel_load(__amdgpu_buffer_rsrc_t rX, __amdgpu_b
     constexpr int RPL = 256 / YW;  // Y rows per load
     constexpr int LPR = YW / 4;    // lanes per Y row
     constexpr unsigned OUT = 0x80000000u;
-    const int lane = threadIdx.x & 63;
+    // The lane's offsets are recomputed at every call (a few VALU
+    // instructions) rather than kept across the product's K loop: the empty
+    // asm hides the thread index's origin from loop-invariant hoisting.
+    // Kept live, they were spilled, and the reload before a load waited for
+    // every load in flight, the previous X panel's included (vmcnt(0)).
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63;
     const int xrow = lane >> 3, xpos = lane & 7;
     for (int i = wave; i < npad / 8; i += NW) {
         const int row = 8 * i + xrow;
@@ -411,27 +468,23 @@ __device__ __forceinline__ void panel_load(__amdgpu_buffer_rsrc_t rX, __amdgpu_b
 }
 
 // Operands of one q step of a K panel: the left operand's 16-byte reads of
-// the wave's CNT blocks and the right operand's values of its two block
-// columns (the second one a copy of the first when all blocks share one).
+// the wave's CNT blocks and the right operand's four values of their block
+// column.
 template <int CNT>
 struct PanelOps {
     f4 a[CNT > 0 ? CNT : 1];
-    float b0[4], b1[4];
+    float b[4];
 };
 
 template <int NPMAX, int CNT, int MB>
 __device__ __forceinline__ void panel_ops(PanelOps<CNT> &o, const float *st, const int (&bi)[MB],
-                                          int col0, int col1, int q) {
+                                          int col, int q) {
     constexpr int YW = NPMAX;
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, l32 = lane & 31;
     const float *ys = st + NPMAX * 32;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int k = 16 * h + 4 * q + t;
-        o.b0[t] = ys[k * YW + col0];
-        o.b1[t] = ys[k * YW + col1];
-    }
+    for (int t = 0; t < 4; ++t) o.b[t] = ys[(16 * h + 4 * q + t) * YW + col];
 #pragma unroll
     for (int j = 0; j < CNT; ++j) {
         const int row = bi[j] * 32 + l32;
@@ -439,29 +492,26 @@ __device__ __forceinline__ void panel_ops(PanelOps<CNT> &o, const float *st, con
     }
 }
 
-// The MFMAs of one K panel for a wave that owns CNT blocks: blocks j < js
-// lie in block column c0, the rest in c0 + 1; bi[j] are their block rows.
-// The q steps are unrolled over two operand sets, so the reads of step
-// q + 1 are in flight while the MFMAs of step q run.
+// The MFMAs of one K panel for a wave that owns CNT blocks of block column
+// c0 (block rows bi[j]).  The q steps are unrolled over two operand sets, so
+// the reads of step q + 1 are in flight while the MFMAs of step q run.
 template <int NPMAX, int CNT, int MB>
 __device__ __forceinline__ void panel_mfma(v16f (&acc)[MB], const float *st, const int (&bi)[MB],
-                                           int c0, int js) {
+                                           int c0) {
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, l32 = lane & 31;
-    const int col0 = (c0 * 32 + l32) ^ (32 * h);
-    const int col1 = js < CNT ? ((c0 + 1) * 32 + l32) ^ (32 * h) : col0;
+    const int col = (c0 * 32 + l32) ^ (32 * h);
     PanelOps<CNT> ops[2];
-    panel_ops<NPMAX, CNT, MB>(ops[0], st, bi, col0, col1, 0);
+    panel_ops<NPMAX, CNT, MB>(ops[0], st, bi, col, 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (q < 3) panel_ops<NPMAX, CNT, MB>(ops[(q + 1) & 1], st, bi, col0, col1, q + 1);
+        if (q < 3) panel_ops<NPMAX, CNT, MB>(ops[(q + 1) & 1], st, bi, col, q + 1);
         const PanelOps<CNT> &o = ops[q & 1];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int j = 0; j < CNT; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a[j][t], j < js ? o.b0[t] : o.b1[t],
-                                                              acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a[j][t], o.b[t], acc[j], 0, 0, 0);
     }
 }
 
@@ -469,7 +519,7 @@ __device__ __forceinline__ void panel_mfma(v16f (&acc)[MB], const float *st, con
 // zero padded), for a wave with CNT blocks.  Ends with a workgroup barrier
 // after the last panel.
 template <int NPMAX, int NW, int CNT, int MB>
-__device__ __forceinline__ void panel_product(v16f (&acc)[MB], const int (&bi)[MB], int c0, int js,
+__device__ __forceinline__ void panel_product(v16f (&acc)[MB], const int (&bi)[MB], int c0,
                                               int npad, const float *X, const float *Y, float *L0,
                                               float *L1, int wave) {
     const int nb = npad / 32;
@@ -487,32 +537,32 @@ __device__ __forceinline__ void panel_product(v16f (&acc)[MB], const int (&bi)[M
     __syncthreads();
     for (int kt = 0; kt < nb; kt += 2) {
         if (kt + 1 < nb) panel_load<NPMAX, NW>(rX, rY, npad, kt + 1, L1, wave);
-        panel_mfma<NPMAX, CNT, MB>(acc, L0, bi, c0, js);
+        panel_mfma<NPMAX, CNT, MB>(acc, L0, bi, c0);
         __builtin_amdgcn_s_waitcnt(0x0f70);
         __syncthreads();
         if (kt + 1 < nb) {
             if (kt + 2 < nb) panel_load<NPMAX, NW>(rX, rY, npad, kt + 2, L0, wave);
-            panel_mfma<NPMAX, CNT, MB>(acc, L1, bi, c0, js);
+            panel_mfma<NPMAX, CNT, MB>(acc, L1, bi, c0);
             __builtin_amdgcn_s_waitcnt(0x0f70);
             __syncthreads();
         }
     }
 }
 
-// The power's products for a wave with CNT blocks (CNT fixed, so the K
-// loop is fully unrolled over the blocks); see wg_power_panel.
+// The power's products for a wave with CNT blocks, block rows r0 .. r0 +
+// CNT - 1 of block column c0 (CNT fixed, so the K loop is fully unrolled
+// over the blocks); see wg_power_panel.
 template <int NPMAX, int NW, int CNT, int MB>
 __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t p, float *out,
                                                  double *scale, float *SX, float *SAm, float *L0,
-                                                 float *L1, double *red, int eA, int t0, int wave) {
+                                                 float *L1, double *red, int eA, int c0, int r0,
+                                                 int wave) {
     const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
-    const int npad = wg_npad(n), nb = npad / 32;
-    const int c0 = t0 / nb;
-    const int js = (c0 + 1) * nb - t0;  // blocks in column c0
+    const int npad = wg_npad(n);
     int bi[MB];
 #pragma unroll
-    for (int j = 0; j < MB; ++j) bi[j] = j < js ? t0 - c0 * nb + j : j - js;
-    auto bcol = [&](int j) { return j < js ? c0 : c0 + 1; };
+    for (int j = 0; j < MB; ++j) bi[j] = r0 + j;
+    auto bcol = [&](int) { return c0; };
 
     const int top = 63 - __clzll((unsigned long long)p);
     int eX = eA;
@@ -525,8 +575,8 @@ __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t 
             if (mul && !((p >> bit) & 1)) break;
             const bool last = bit == 0 && (mul || !(p & 1));
             const float *left = first ? SAm : SX;
-            panel_product<NPMAX, NW, CNT, MB>(acc, bi, c0, js, npad, left, mul ? SAm : left, L0,
-                                              L1, wave);
+            panel_product<NPMAX, NW, CNT, MB>(acc, bi, c0, npad, left, mul ? SAm : left, L0, L1,
+                                              wave);
             first = false;
             double ss = 0.0;
 #pragma unroll
@@ -580,6 +630,8 @@ __device__ __forceinline__ void wg_power_panel(const float *A, int n, int64_t p,
     static_assert(NPMAX == 64 || NPMAX == 128 || NPMAX == 256, "panel widths");
     constexpr int NT = NW * 64;
     constexpr int MB = (NPMAX / 32) * (NPMAX / 32) / NW > 0 ? (NPMAX / 32) * (NPMAX / 32) / NW : 1;
+    static_assert(MB <= 4, "the dispatch below covers up to four blocks per wave");
+    static_assert(NW == 16 || NPMAX <= 128, "the eight-wave piece table covers nb <= 4");
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     double SA;
@@ -595,16 +647,16 @@ __device__ __forceinline__ void wg_power_panel(const float *A, int n, int64_t p,
     __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
 
-    // this wave's range of the column-major block order
-    const int T = nb * nb;
-    const int rank = (NW / 4) * (wave & 3) + (wave >> 2);  // waves w, w + 4, ... share a SIMD
-    const int t0 = T * rank / NW, cnt = T * (rank + 1) / NW - t0;
+    // this wave's piece of the block grid: cnt blocks from block row r0 of
+    // block column c0
+    const unsigned pc = NW == 16 ? kPieces16[nb - 1][wave] : kPieces8[nb - 1][wave];
+    const int c0 = pc & 15, r0 = (pc >> 4) & 15, cnt = pc >> 8;
     // every wave takes part in the barriers of every product, whatever its count
 #define MPOW_PANEL_CASE(C)                                                                          \
     case C:                                                                                         \
         if constexpr (C <= MB)                                                                      \
             panel_power_body<NPMAX, NW, C, (C < 1 ? 1 : C)>(A, n, p, out, scale, SX, SAm, L0, L1,   \
-                                                            red, eA, t0, wave);                     \
+                                                            red, eA, c0, r0, wave);                 \
         break;
     switch (cnt) {
         MPOW_PANEL_CASE(0)
@@ -612,10 +664,6 @@ __device__ __forceinline__ void wg_power_panel(const float *A, int n, int64_t p,
         MPOW_PANEL_CASE(2)
         MPOW_PANEL_CASE(3)
         MPOW_PANEL_CASE(4)
-        MPOW_PANEL_CASE(5)
-        MPOW_PANEL_CASE(6)
-        MPOW_PANEL_CASE(7)
-        MPOW_PANEL_CASE(8)
         default: break;
     }
 #undef MPOW_PANEL_CASE
