@@ -290,6 +290,9 @@ mpow_status mpow_plan_tile_table(mpow_plan_t plan, int *table, int len, int set)
  * ragged batch (sizes uniform over the buckets, p log-uniform in [2, 1000]):
  * the per-bucket winners, the table before tuning, and each single shape for
  * all sizes; the fastest becomes the plan's tile table.
+ * Timing starts after a few tenths of a second of warm-up work (an idle GPU
+ * runs at a lower clock at first), and the candidates of each choice are
+ * timed round-robin, each keeping its fastest run.
  * If cache_path is non-NULL and holds choices written for the same GPU model
  * (architecture and CU count) and mode that cover everything this plan tunes,
  * they are loaded instead (unless MPOW_TUNE_FORCE); otherwise the fresh

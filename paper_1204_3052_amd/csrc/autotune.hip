@@ -7,7 +7,10 @@
 //  - the single-matrix product kernel per 256-wide size bucket (every plan):
 //    each candidate tile of the plan's mode is timed on one product.
 // Every candidate adds each output's products in the same order, so tuning
-// changes speed only, never a result.
+// changes speed only, never a result.  Timing starts after a warm-up of a
+// few tenths of a second (an idle GPU's clock ramps up under load), and the
+// candidates of one choice are timed round-robin, each keeping its fastest
+// run, so that none is favoured by its place in the order.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +26,7 @@ namespace {
 constexpr int kBuckets = kTileBuckets;
 constexpr int kShapes = kBatchShapes;  // tile shape ids of the batched kernel, all timed
 constexpr int64_t kTuneP = 100;        // power of the timing batches (8 products)
+static_assert(2 + kShapes <= 8, "Timer::fastest holds at most eight candidates");
 constexpr int kPickMaxN = 256 * (kPickBuckets - 1);  // largest size with a tuned pick
 
 struct DevGuard {
@@ -156,19 +160,49 @@ struct Timer {
         if (e1) (void)hipEventDestroy(e1);
         if (s) (void)hipStreamDestroy(s);
     }
-    // Fastest of reps timed runs of fn(s) after one untimed run; < 0 on error.
+    // One timed run of fn(s) in ms; < 0 on error.
     template <typename Fn>
-    float best_ms(int reps, Fn fn) {
-        float t_min = 1e30f;
-        for (int rep = 0; rep <= reps; ++rep) {
-            float ms = 0.f;
-            if (hipEventRecord(e0, s) != hipSuccess || fn(s) != hipSuccess ||
-                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                return -1.f;
-            if (rep > 0 && ms < t_min) t_min = ms;
-        }
-        return t_min;
+    float once_ms(Fn fn) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess || fn(s) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return -1.f;
+        return ms;
+    }
+    // Runs fn(s) for at least `seconds` of device time (and at least once):
+    // the clock of a GPU that was idle runs low for its first few hundred
+    // milliseconds of work, which would favour the candidates timed last.
+    template <typename Fn>
+    bool warm(float seconds, Fn fn) {
+        float total = 0.f;
+        do {
+            const float ms = once_ms(fn);
+            if (ms < 0.f) return false;
+            total += ms;
+        } while (total < 1e3f * seconds);
+        return true;
+    }
+    // Index of the fastest of nc candidates: select(c) makes candidate c
+    // current, fn(s) runs it; every round times each candidate once, in
+    // turn (one untimed round first), and a candidate's time is its fastest.
+    // -1 on error.
+    template <typename Select, typename Fn>
+    int fastest(int nc, int rounds, Select select, Fn fn, float *best_ms = nullptr) {
+        float t[8];
+        for (int c = 0; c < nc; ++c) t[c] = 1e30f;
+        for (int r = 0; r <= rounds; ++r)
+            for (int c = 0; c < nc; ++c) {
+                select(c);
+                const float ms = once_ms(fn);
+                if (ms < 0.f) return -1;
+                if (r > 0 && ms < t[c]) t[c] = ms;
+            }
+        int b = 0;
+        for (int c = 1; c < nc; ++c)
+            if (t[c] < t[b]) b = c;
+        if (best_ms) *best_ms = t[b];
+        return b;
     }
 };
 
@@ -214,21 +248,13 @@ mpow_status tune_batch(mpow_plan *plan, Timer &tm) {
         return batch_enqueue(&plan->batch, count, Ap.data(), nv.data(), pv.data(), Op.data(), nullptr,
                              s, false, nullptr);
     };
+    for (int i = 0; i < count; ++i) nv[i] = bmax;
+    if (st == MPOW_SUCCESS && !tm.warm(0.4f, batch)) st = MPOW_ERR_DEVICE;
     for (int b = 1; st == MPOW_SUCCESS && b * 16 <= bmax; ++b) {
         for (int i = 0; i < count; ++i) nv[i] = b * 16;
-        float best = 1e30f;
         const int prev = plan->batch.cfg[b];
-        int best_shape = prev;
-        for (int shape = 0; shape < kShapes && st == MPOW_SUCCESS; ++shape) {
-            plan->batch.cfg[b] = shape;
-            const float ms = tm.best_ms(3, batch);
-            if (ms < 0.f) {
-                st = MPOW_ERR_DEVICE;
-            } else if (ms < best) {
-                best = ms;
-                best_shape = shape;
-            }
-        }
+        const int best_shape = tm.fastest(kShapes, 3, [&](int c) { plan->batch.cfg[b] = c; }, batch);
+        if (best_shape < 0) st = MPOW_ERR_DEVICE;
         plan->batch.cfg[b] = st == MPOW_SUCCESS ? best_shape : prev;
     }
 
@@ -253,19 +279,14 @@ mpow_status tune_batch(mpow_plan *plan, Timer &tm) {
         int ntab = 2;
         for (int shape = 0; shape < kShapes; ++shape, ++ntab)
             for (int b = 0; b < kBuckets; ++b) tables[ntab][b] = b == 0 ? before[0] : shape;
-        float best = 1e30f;
-        int best_t = 1;
-        for (int t = 0; t < ntab && st == MPOW_SUCCESS; ++t) {
-            for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = tables[t][b];
-            const float ms = tm.best_ms(2, batch);
-            if (ms < 0.f) {
-                st = MPOW_ERR_DEVICE;
-            } else if (ms < best) {
-                best = ms;
-                best_t = t;
-            }
+        int best_t = tm.fastest(
+            ntab, 2, [&](int t) { for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = tables[t][b]; },
+            batch);
+        if (best_t < 0) {
+            st = MPOW_ERR_DEVICE;
+            best_t = 1;
         }
-        for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = tables[st == MPOW_SUCCESS ? best_t : 1][b];
+        for (int b = 0; b < kBuckets; ++b) plan->batch.cfg[b] = tables[best_t][b];
     }
     if (st == MPOW_SUCCESS && batch_wait_all(&plan->batch) != hipSuccess) st = MPOW_ERR_DEVICE;
     (void)hipFree(in);
@@ -300,23 +321,15 @@ mpow_status tune_picks(mpow_plan *plan, Timer &tm) {
     int ids[4];
     const int nc = pick_candidates(plan->mode, ids);
     Workspace ws = plan->ws;  // the plan's buffers with each candidate forced
+    int n = 256 * last;
+    auto power = [&](hipStream_t s) { return enqueue_power(ws, in, n, 2, out, nullptr, s, nullptr); };
+    ws.kernel = ids[0];
+    if (st == MPOW_SUCCESS && !tm.warm(0.3f, power)) st = MPOW_ERR_DEVICE;
     for (int b = first; st == MPOW_SUCCESS && b <= last; ++b) {
-        const int n = 256 * b;
-        float best = 1e30f;
-        int best_id = -1;
-        for (int c = 0; c < nc && st == MPOW_SUCCESS; ++c) {
-            ws.kernel = ids[c];
-            const float ms = tm.best_ms(2, [&](hipStream_t s) {
-                return enqueue_power(ws, in, n, 2, out, nullptr, s, nullptr);
-            });
-            if (ms < 0.f) {
-                st = MPOW_ERR_DEVICE;
-            } else if (ms < best) {
-                best = ms;
-                best_id = ids[c];
-            }
-        }
-        if (st == MPOW_SUCCESS) plan->ws.pick1[b] = (int8_t)(best_id + 1);
+        n = 256 * b;
+        const int c = tm.fastest(nc, 2, [&](int k) { ws.kernel = ids[k]; }, power);
+        if (c < 0) st = MPOW_ERR_DEVICE;
+        else plan->ws.pick1[b] = (int8_t)(ids[c] + 1);
     }
     (void)hipFree(in);
     (void)hipFree(out);
