@@ -264,9 +264,15 @@ def batched_workload(args):
     hb = mpow.mpow_plan_create(0, 256, count, mpow.MPOW_FP32, 0)
     hp = mpow.mpow_plan_create(0, 256, 0, mpow.MPOW_FP32, 0)
     default_table = mpow.mpow_plan_tile_table(hb)
+    # the tiled shapes for comparison: per size the tile that pads n least
+    # (64 x 64 up to n = 64), every product through the workers' scratch
+    tiles_table = [1] + [1 if 16 * b <= 64 else (0 if (16 * b + 127) // 128 * 128 <= (16 * b + 63) // 64 * 64 else 1)
+                         for b in range(1, mpow.TILE_TABLE_LEN)]
     t0 = time.perf_counter()
     if args.tile_shape >= 0:  # one fixed tile shape for every size, no tuning
         mpow.mpow_plan_tile_table(hb, [args.tile_shape] * mpow.TILE_TABLE_LEN)
+    elif args.tile_shape == -2:
+        mpow.mpow_plan_tile_table(hb, tiles_table)
     elif args.tile_shape == -1:
         mpow.mpow_plan_autotune(hb, None, mpow.MPOW_TUNE_FORCE)
     tune_s = time.perf_counter() - t0
@@ -285,8 +291,8 @@ def batched_workload(args):
             mpow.mpow_run(hp, a_ptrs[i], nl[i], pl[i], o_ptrs[i], sc[i:i + 1].data_ptr(), stream.cuda_stream)
 
     res = {}
-    def batched_default():
-        mpow.mpow_plan_tile_table(hb, default_table)
+    def batched_tiles():
+        mpow.mpow_plan_tile_table(hb, tiles_table)
         batched()
         mpow.mpow_plan_tile_table(hb, tuned_table)
 
@@ -294,7 +300,7 @@ def batched_workload(args):
     # host prepares each batch while the previous ones run, as a serving loop
     # would), ms per batch = elapsed / K.  The loop of plain calls is timed
     # the same way, one pass per step.
-    legs = [("batched", batched), ("batched_untuned", batched_default), ("loop_plain", looped)]
+    legs = [("batched", batched), ("batched_tiles", batched_tiles), ("loop_plain", looped)]
     if args.tile_shape != -1 or args.batch_n > 0:
         legs = legs[:1]
     for name, fn in legs:
@@ -333,7 +339,7 @@ def batched_workload(args):
                           "p log-uniform [2,1000], graph-replayed persistent launches "
                           "(one per kernel instance the tile table needs)",
               "effective_gflop_per_batch": round(flop / 1e9, 2), "results": res,
-              "tile_table": {"tuned": tuned_table[1:], "default": default_table[1:],
+              "tile_table": {"tuned": tuned_table[1:], "default": default_table[1:], "tiles": tiles_table[1:],
                              "tune_seconds": round(tune_s, 2)},
               "speedup_vs_loop": (round(res["loop_plain"]["ms"] / res["batched"]["ms"], 2)
                                   if "loop_plain" in res else None)}
@@ -912,7 +918,7 @@ def main():
                     help="batched workload: every matrix of this size instead of the ragged sizes")
     ap.add_argument("--tile-shape", type=int, default=-1,
                     help="batched workload: this tile shape (0-4) for every size instead of "
-                         "tuning; -2: the untuned default table")
+                         "tuning; -2: the tiled shapes (per size the tile that pads n least)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (for HBM counter scaling)")
     args = ap.parse_args()

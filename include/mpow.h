@@ -264,6 +264,9 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
  * CU; with shape 0 and every such matrix allowing 16-byte loads, n % 4 == 0
  * and a 16-byte aligned A, the instance whose tiles load straight into
  * LDS), and each whole-power form on its own instance.
+ * A plan starts with shape 4 for every size (on MI355X the fastest at every
+ * size of uniform batches and on ragged batches); mpow_plan_autotune may
+ * replace it with measured choices.
  * set = 0 copies the plan's table into table[0..16]; set = 1 replaces it.
  * len must be >= 17.
  * Errors: INVALID (plan NULL or without batch support, len < 17, a shape

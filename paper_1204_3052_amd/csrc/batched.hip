@@ -394,12 +394,11 @@ __global__ __launch_bounds__(PanelWaves<NPMAX>::NW * 64) void batched_wg_panel_k
 
 }  // namespace
 
-// Default tile shape before tuning: the one that pads n least, larger on ties.
-int batched_cfg_for(int n) {
-    if (n <= 64) return 1;
-    const int p128 = (n + 127) / 128 * 128, p64 = (n + 63) / 64 * 64;
-    return p128 * p128 <= p64 * p64 ? 0 : 1;
-}
+// Default tile shape before tuning: the streamed-panel whole-power form for
+// every size, which on MI355X beat the tiled shapes at every size of uniform
+// batches of 4096 matrices (by 1% at n = 128 up to 73% at n = 160) and on
+// ragged batches.
+int batched_cfg_for(int) { return 4; }
 
 int batched_occupancy(int inst) {
     int blocks = 0;
