@@ -54,8 +54,9 @@ def test_gemm_counts_for_named_sizes():
 
 
 def test_paper_powers_take_log2_products():
-    # Section 4.3: the method multiplies "log(N)" times instead of N times; the
-    # powers timed in section 5.2 are 64..1024, all powers of two.
+    # Section 4.3: the method's product count is logarithmic in the power
+    # rather than linear; the powers timed in section 5.2 are 64..1024, all
+    # powers of two.
     for p in (64, 128, 256, 512, 1024):
         assert O.gemm_count(p) == int(math.log2(p))
 
