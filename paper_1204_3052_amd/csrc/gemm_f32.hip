@@ -20,7 +20,9 @@ __device__ __forceinline__ OperandExps operand_exponents(const GemmLaunch &g, do
     const int eX =
         g.partX ? exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
     int eY = eX;
-    if (!g.partY)
+    if (g.eYin)
+        eY = *g.eYin;
+    else if (!g.partY)
         eY = g.eYfix;
     else if (g.partY != g.partX)
         eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));

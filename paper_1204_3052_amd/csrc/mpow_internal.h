@@ -161,6 +161,9 @@ struct GemmLaunch {
     int *eSlotY = nullptr;   // where block 0 records eY (may be null)
     // partX / partY null: the operand's exponent is eXfix / eYfix instead
     int eXfix = 0, eYfix = 0;
+    // non-null: eY is read from here (recorded by an earlier launch on the
+    // stream) instead of being reduced from partY
+    const int *eYin = nullptr;
     float alpha = 1.0f;      // the identity-adding epilogue: C = alpha X'Y' + I
 };
 

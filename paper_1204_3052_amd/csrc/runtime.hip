@@ -216,6 +216,11 @@ int schedule_of(int64_t p, uint8_t *ops) {
 
 // Float32 products: step k computes C_k = (2^-e X)(2^-e' Y) from the
 // partial sums of its operands; X = C_{k-1} (C_0 = A), Y = X (square) or A.
+// The first step is always A^2, whose launch records e_A in the first
+// exponent slot; the multiplies read e_A from there rather than reducing A's
+// partial sums again (one device load instead of a workgroup-wide reduction
+// of hundreds of partials, whose latency every workgroup of a small product
+// pays).
 hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const uint8_t *ops,
                     int G, int nbA, float *out, double *log2_scale, hipStream_t s,
                     TimingSink *timing) {
@@ -238,8 +243,9 @@ hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const
             g.nPartY = nPartX;
         } else {
             g.Y = A;
-            g.partY = ws.partA;
-            g.nPartY = nbA;
+            g.partY = nullptr;
+            g.nPartY = 0;
+            g.eYin = ws.escale;  // e_A, recorded by step 1 (A^2)
         }
         g.C = ws.buf[k & 1];
         g.partC = ws.part[k & 1];
