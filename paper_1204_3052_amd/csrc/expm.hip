@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kNT) void taylor_start_kernel(const float *__restri
 __global__ __launch_bounds__(kNT) void norm_exponent_kernel(const double *__restrict__ part,
                                                             int nPart, int *__restrict__ e) {
     __shared__ double red[kNT];
-    const double S = block_sum_partials<kNT>(part, nPart, red);
+    const double S = sum_partials<kNT>(part, nPart, red);
     if (threadIdx.x == 0) *e = (S > 0.0 && isfinite(S)) ? exponent_of_sumsq(S) : INT_MIN;
 }
 

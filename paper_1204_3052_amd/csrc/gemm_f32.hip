@@ -18,14 +18,14 @@ namespace {
 template <int NT>
 __device__ __forceinline__ OperandExps operand_exponents(const GemmLaunch &g, double *red) {
     const int eX =
-        g.partX ? exponent_of_sumsq(block_sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
+        g.partX ? exponent_of_sumsq(sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
     int eY = eX;
     if (g.eYin)
         eY = *g.eYin;
     else if (!g.partY)
         eY = g.eYfix;
     else if (g.partY != g.partX)
-        eY = exponent_of_sumsq(block_sum_partials<NT>(g.partY, g.nPartY, red));
+        eY = exponent_of_sumsq(sum_partials<NT>(g.partY, g.nPartY, red));
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (g.eSlot) *g.eSlot = eX;
         if (g.eSlotY) *g.eSlotY = eY;

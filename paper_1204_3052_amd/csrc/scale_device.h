@@ -75,6 +75,23 @@ __device__ __forceinline__ double wave_sum_partials(const double *__restrict__ p
     return __shfl(acc, 0, 64);
 }
 
+// Sum of `count` float64 partials in a fixed order, returned to every thread
+// of the block: up to 1024 partials each wave sums them all itself
+// (wave_sum_partials: at most 16 loads per lane and a six-step shuffle tree,
+// no barrier), more by the block's tree (block_sum_partials, nine barriers
+// at 512 threads).  The choice depends on count alone, so every block of a
+// launch adds in the same order.  For the partials of a small product the
+// block's tree of barriers was a large part of the time a workgroup spends
+// before its first MFMA: chains of products at n <= 256 ran 10-12% faster
+// without it.  All threads of the block must call it (it may contain
+// barriers).
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int count,
+                                               double *red) {
+    if (count <= 1024) return wave_sum_partials(part, count);
+    return block_sum_partials<NT>(part, count, red);
+}
+
 // Tile order for a grid of tilesM x tilesN output tiles.  Workgroups are
 // dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8), and
 // each XCD has its own L2.  The block index is first permuted so that every

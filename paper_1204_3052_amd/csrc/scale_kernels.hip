@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kNT) void finish_kernel(const float *C, int n,
     __shared__ double sh_sG;
     __shared__ int sh_eG;
     __shared__ int sh_zero;
-    const double S = block_sum_partials<kNT>(partC, nPartC, red);
+    const double S = sum_partials<kNT>(partC, nPartC, red);
     if (threadIdx.x == 0) {
         double s = 0.0;
         if (naive_steps > 0) {
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kNT) void finish_graph_kernel(const float *C, int n
     __shared__ double red[kNT];
     __shared__ double sh_sG;
     __shared__ int sh_eG;
-    const double S = block_sum_partials<kNT>(partC, nPartC, red);
+    const double S = sum_partials<kNT>(partC, nPartC, red);
     if (threadIdx.x == 0) {
         double s[kSlots];
         for (int i = 0; i < kSlots; ++i) s[i] = 0.0;

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void split_kernel(SplitLaunch s) {
         }
     }
 
-    const int eX = exponent_of_sumsq(block_sum_partials<256>(s.part, s.nPart, red));
+    const int eX = exponent_of_sumsq(sum_partials<256>(s.part, s.nPart, red));
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0 && s.eSlot) *s.eSlot = eX;
     const PowScale f = pow2_neg(eX - Tr::kShift);
 
