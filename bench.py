@@ -774,7 +774,9 @@ def paper_workload(args):
         if n not in cpu_product_s:
             cpu_product_s[n] = sequential_product_seconds(A_np)
         cpu_s = cpu_product_s[n] * (p - 1)
+        gf = gemm_count(p) * 2.0 * n ** 3 / res["ours"] / 1e9
         rows.append({"n": n, "p": p, "ours_s": round(res["ours"], 6), "naive_gpu_s": round(res["naive_gpu"], 6),
+                     "ours_gflops": round(gf, 1), "ours_pct_fp32_mfma_peak": round(gf / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 3),
                      "ours_vs_naive_gpu": round(res["naive_gpu"] / res["ours"], 1),
                      "seq_cpu_s_extrapolated": round(cpu_s, 3),
                      "ours_vs_seq_cpu": round(cpu_s / res["ours"], 0),
