@@ -1085,6 +1085,11 @@ def main():
         cpu, errs = oracle_leg(cases, kept)
         result["cpu_baseline"] = cpu
         result["cpu_baseline_one_core"] = oracle_one_core(cases)
+        # the same work's rate against the oracle on the host's cores, beside
+        # the paper's own headline figures on a Tesla C2050 (abstract: over
+        # its sequential CPU code and over its naive GPU kernel), context only
+        result["vs_cpu_baseline"] = round(value / cpu["value"], 1)
+        result["paper_context_c2050"] = {"vs_sequential_cpu": 1000, "vs_naive_gpu": 44}
         for c in per_case:
             e = errs.get((c["n"], c["p"]))
             c["rel_err"] = float(f"{e[0]:.3e}") if e else None
