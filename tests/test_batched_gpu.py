@@ -248,6 +248,16 @@ def test_batched_invalid_arguments(plans):
     torch.cuda.synchronize()
 
 
+def test_default_table_is_panel_form(plans):
+    # a plan starts with the streamed-panel whole-power form (shape 4) for
+    # every size; tuning may replace it
+    h = mpow.mpow_plan_create(0, 256, 8, mpow.MPOW_FP32, 0)
+    try:
+        assert mpow.mpow_plan_tile_table(h)[1:] == [4] * (mpow.TILE_TABLE_LEN - 1)
+    finally:
+        mpow.mpow_plan_destroy(h)
+
+
 def test_tile_shapes_bit_identical(plans):
     hb, _ = plans
     mats, ps = edge_batch(5)
