@@ -275,8 +275,10 @@ namespace mpow {
 // its MFMAs without a barrier.  Wave w takes the 32-wide K slices w, w + 4,
 // w + 8, ... in ascending order and the four partial tiles are added in wave
 // order, as the register-staged 32 x 32 tile with a 4-way K split does, so
-// the two give the same bits (and the operand scales are applied as in
-// f32_tile_dma).  Layouts: a stage's X block is 32 rows of 128 floats, 16-byte
+// the two give the same products (and the operand scales are applied as in
+// f32_tile_dma); their tile sums of squares are added in different float64
+// orders, which can move the next exponent only for a sum within rounding
+// of a power of four.  Layouts: a stage's X block is 32 rows of 128 floats, 16-byte
 // chunk c of row r at position c ^ (r & 15); its Y block is 128 rows of 32
 // floats, row k at float 32 k + 32 (k / 16) (a gap of 32 floats after every
 // 16 rows), so the lane halves' reads (rows k and k + 16) use different LDS
@@ -377,37 +379,41 @@ __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
         }
     }
 
-    // Waves 1..3 park their partial tiles in the first X block; wave 0 adds
-    // them in wave order.
+    // Every wave parks its partial tile in the first X block; wave w then
+    // finishes rows 8 w + 4 h + i (i < 4) of the tile, register rows 4 w + i:
+    // each element is the four partial tiles added in wave order (the order
+    // of one wave adding the others' into its own), scaled and stored, its
+    // square added to the wave's sum; the waves' sums are then added in
+    // wave order.  Spreading the epilogue over the four waves instead of
+    // leaving it to wave 0 shortens a small product's tail.
     float *park = As[0];
+    double *wred = (double *)Bs[0];
     __syncthreads();
-    if (wave > 0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) park[((wave - 1) * 16 + r) * 64 + lane] = acc[r];
+    for (int r = 0; r < 16; ++r) park[(wave * 16 + r) * 64 + lane] = acc[r];
+    __syncthreads();
+    const PowScale fs = pow2_neg(after ? e.x + e.y : 0);
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * wave + i;
+        float v = park[r * 64 + lane] + park[(16 + r) * 64 + lane];
+        v += park[(32 + r) * 64 + lane];
+        v += park[(48 + r) * 64 + lane];
+        const int row = m0 + 8 * wave + 4 * h + i;
+        const int col = n0 + l32;
+        if (row < n && col < n) {
+            v = v * fs.a * fs.b;
+            if constexpr (AXPI) v = fmaf(v, alpha, row == col ? 1.0f : 0.0f);
+            C[(int64_t)row * n + col] = v;
+            ss += (double)v * (double)v;
+        }
     }
+    ss = wave_sum_lane0(ss);
+    if (lane == 0) wred[wave] = ss;
     __syncthreads();
     double t = 0.0;
-    if (wave == 0) {
-#pragma unroll
-        for (int g = 1; g < 4; ++g)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] += park[((g - 1) * 16 + r) * 64 + lane];
-        const PowScale fs = pow2_neg(after ? e.x + e.y : 0);
-        double ss = 0.0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = m0 + 8 * (r >> 2) + 4 * h + (r & 3);
-            const int col = n0 + l32;
-            if (row < n && col < n) {
-                float v = acc[r] * fs.a * fs.b;
-                if constexpr (AXPI) v = fmaf(v, alpha, row == col ? 1.0f : 0.0f);
-                C[(int64_t)row * n + col] = v;
-                ss += (double)v * (double)v;
-            }
-        }
-        ss = wave_sum_lane0(ss);
-        t = ss;  // valid in thread 0
-    }
+    if (tid == 0) t = ((wred[0] + wred[1]) + wred[2]) + wred[3];  // valid in thread 0
     __syncthreads();  // the LDS blocks may be reused by the caller
     return t;
 }
