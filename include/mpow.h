@@ -329,8 +329,9 @@ mpow_status mpow_plan_set_kernel(mpow_plan_t plan, int kernel);
 /* The float32 product kernel (an MPOW_KERNEL_* id) that mpow_run uses at
  * size n when no kernel is forced: aligned != 0 means a 16-byte aligned A
  * (the LDS-DMA tiles need that and n % 4 == 0).  Host-only, no device call;
- * -1 for n < 1.  Below n = 768 the 32x32 tile with a 4-way K split (its
- * whole-K-in-LDS form up to n = 512); from n = 768 the LDS-DMA tile with the
+ * -1 for n < 1.  Below n = 768 the 32x32 tile with a K split: for a
+ * 16-byte-loadable input up to n = 512 its whole-K-in-LDS form over 8 waves,
+ * otherwise the register-staged form over 4 waves; from n = 768 the LDS-DMA tile with the
  * best estimated rate for how its tile count fills the 256 CUs in whole
  * waves (section 4.3.7's tiled product, tile size chosen per n).  For
  * n <= 64 mpow_run's binary schedule does not launch a product kernel at
@@ -368,7 +369,8 @@ enum {
                                   8-wave workgroup, base and running matrix resident in
                                   LDS (mpow_run only, its default for n <= 64; timing
                                   counts G(p) 2 n^3 per launch) */
-    MPOW_KERNEL_COUNT = 20
+    MPOW_KERNEL_GEMM_F32_32_K8_DMA = 20, /* float32 product, 32x32 tiles, K split over 8 waves, whole K in LDS (n <= 512) */
+    MPOW_KERNEL_COUNT = 21
 };
 
 /* Timing of product launches recorded under MPOW_FLAG_TIMING since the last

@@ -78,10 +78,10 @@ __global__ __launch_bounds__(WM *WN * 64) void gemm_f32_dma_kernel(GemmLaunch g)
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
-// The 32 x 32 tile with a 4-way K split and the whole K range in LDS
-// (f32_tile_dma_k4), for n <= DMA_K4_MAX_N with 16-byte loads.
-template <bool AXPI>
-__global__ __launch_bounds__(256) void gemm_f32_dma_k4_kernel(GemmLaunch g) {
+// The 32 x 32 tile with a KS-way K split (KS = 4 or 8 waves) and the whole K
+// range in LDS (f32_tile_dma_k4), for n <= DMA_K4_MAX_N with 16-byte loads.
+template <int KS, bool AXPI>
+__global__ __launch_bounds__(KS * 64) void gemm_f32_dma_k4_kernel(GemmLaunch g) {
     static_assert(DMA_K4_STAGES == 4, "one LDS array per stage below");
     __shared__ __attribute__((aligned(16))) float A0[DMA_K4_A_STAGE];
     __shared__ __attribute__((aligned(16))) float A1[DMA_K4_A_STAGE];
@@ -91,16 +91,16 @@ __global__ __launch_bounds__(256) void gemm_f32_dma_k4_kernel(GemmLaunch g) {
     __shared__ __attribute__((aligned(16))) float B1[DMA_K4_B_STAGE];
     __shared__ __attribute__((aligned(16))) float B2[DMA_K4_B_STAGE];
     __shared__ __attribute__((aligned(16))) float B3[DMA_K4_B_STAGE];
-    __shared__ double red[256];
+    __shared__ double red[KS * 64];
 
     const int n = g.n;
     int tm, tn;
     tile_of_block(blockIdx.x, (n + 31) / 32, (n + 31) / 32, &tm, &tn);
     float *const As[4] = {A0, A1, A2, A3};
     float *const Bs[4] = {B0, B1, B2, B3};
-    auto exps = [&]() { return operand_exponents<256>(g, red); };
+    auto exps = [&]() { return operand_exponents<KS * 64>(g, red); };
     const double ss =
-        f32_tile_dma_k4<AXPI>(g.X, g.Y, exps, g.C, n, tm * 32, tn * 32, As, Bs, g.alpha);
+        f32_tile_dma_k4<KS, AXPI>(g.X, g.Y, exps, g.C, n, tm * 32, tn * 32, As, Bs, g.alpha);
     if (threadIdx.x == 0) g.partC[blockIdx.x] = ss;
 }
 
@@ -125,7 +125,8 @@ constexpr Variant kVariants[] = {
     {MPOW_KERNEL_GEMM_F32_64_DMA, 64, 64, 2, 2, 1, "gemm_f32_dma_kernel<64,64,2,2>"},
     {MPOW_KERNEL_GEMM_F32_128_DMA, 128, 128, 4, 2, 1, "gemm_f32_dma_kernel<128,128,4,2>"},
     {MPOW_KERNEL_GEMM_F32_256x128_DMA, 256, 128, 4, 2, 1, "gemm_f32_dma_kernel<256,128,4,2>"},
-    {MPOW_KERNEL_GEMM_F32_32_K4_DMA, 32, 32, 1, 1, 4, "gemm_f32_dma_k4_kernel"},
+    {MPOW_KERNEL_GEMM_F32_32_K4_DMA, 32, 32, 1, 1, 4, "gemm_f32_dma_k4_kernel<4>"},
+    {MPOW_KERNEL_GEMM_F32_32_K8_DMA, 32, 32, 1, 1, 8, "gemm_f32_dma_k4_kernel<8>"},
 };
 
 const Variant *variant(int id) {
@@ -154,26 +155,23 @@ hipError_t launch_variant(const GemmLaunch &g, bool vec4, bool axpi, hipStream_t
 
 }  // namespace
 
-// Default product kernel per size (measured on MI355X, time per product with
-// each kernel forced): below 640 the output tiles alone cannot fill 256 CUs,
-// so 32x32 tiles with the K range split over 4 waves (n = 512: 10.5 us
-// against 19.2 us for 64x64 tiles); 64x64 tiles with a 2-way K split up to
-// 1792 (n = 1024: 29 us against 35 us); 128x128 tiles with a 2-way K split
-// around 2048 (153 us against 172 us); 64x64 tiles up to 4096 (n = 3072:
-// 549 us against 597 us for 128x64); 256x256 tiles from 4096 on.
-// Default product kernel per size.  Small n: 32 x 32 tiles with a 4-way K
-// split (more workgroups than output tiles), with the whole K range loaded
-// into LDS at once where n <= 512 and the loads can be 16 bytes.  From n = 768 with
-// 16-byte loads: the LDS-DMA tile whose estimated rate is highest, the
-// estimate being the tile's rate when every CU runs whole waves of tiles
-// (measured on MI355X products at n = 4096 ... 8192) times the fraction of
-// the last wave of workgroups that is filled:
+// Default product kernel per size.  Below n = 768 the output tiles alone
+// cannot fill 256 CUs, so 32 x 32 tiles with the K range split over several
+// waves (more work per output tile): with 16-byte loads and n <= 512 the
+// whole-K-in-LDS form with 8 waves (chains of products measured on MI355X
+// with each kernel forced: n = 512, p = 1023 in 0.146 ms against 0.153 ms
+// with 4 waves and 0.177-0.181 ms for the register-staged forms; n = 384:
+// 0.125 against 0.130 ms), otherwise the register-staged tile with 4 waves.
+// From n = 768 with 16-byte loads: the LDS-DMA tile whose estimated rate is
+// highest, the estimate being the tile's rate when every CU runs whole waves
+// of tiles (measured on MI355X products at n = 4096 ... 8192) times the
+// fraction of the last wave of workgroups that is filled:
 //   rate = R * (T / 256) / ceil(T / 256),   T = tiles of the n x n output.
 // Against per-size measurements from n = 768 to 8192 this picks the fastest
 // LDS-DMA tile, or one within 2% of it.
 int gemm_pick(int n, bool vec4) {
     if (n < 768)
-        return (vec4 && n <= DMA_K4_MAX_N) ? MPOW_KERNEL_GEMM_F32_32_K4_DMA
+        return (vec4 && n <= DMA_K4_MAX_N) ? MPOW_KERNEL_GEMM_F32_32_K8_DMA
                                            : MPOW_KERNEL_GEMM_F32_32_K4;
     if (vec4 && n <= DMA_MAX_N) {
         struct Cand {
@@ -238,6 +236,8 @@ int gemm_resolve(int kernel, int n, bool vec4) {
         case MPOW_KERNEL_GEMM_F32_256x128_DMA: return dma ? kernel : MPOW_KERNEL_GEMM_F32_128;
         case MPOW_KERNEL_GEMM_F32_32_K4_DMA:
             return vec4 && n <= DMA_K4_MAX_N ? kernel : MPOW_KERNEL_GEMM_F32_32_K4;
+        case MPOW_KERNEL_GEMM_F32_32_K8_DMA:
+            return vec4 && n <= DMA_K4_MAX_N ? kernel : MPOW_KERNEL_GEMM_F32_32_K8;
         default: return kernel;
     }
 }
@@ -266,9 +266,18 @@ hipError_t gemm_launch(int kernel, const GemmLaunch &g, bool vec4, hipStream_t s
             if (!vec4 || g.n > DMA_K4_MAX_N) return hipErrorInvalidValue;  // unresolved id
             const dim3 grid(gemm_tiles(kernel, g.n)), block(256);
             if (axpi)
-                hipLaunchKernelGGL(gemm_f32_dma_k4_kernel<true>, grid, block, 0, s, g);
+                hipLaunchKernelGGL((gemm_f32_dma_k4_kernel<4, true>), grid, block, 0, s, g);
             else
-                hipLaunchKernelGGL(gemm_f32_dma_k4_kernel<false>, grid, block, 0, s, g);
+                hipLaunchKernelGGL((gemm_f32_dma_k4_kernel<4, false>), grid, block, 0, s, g);
+            return hipGetLastError();
+        }
+        case MPOW_KERNEL_GEMM_F32_32_K8_DMA: {
+            if (!vec4 || g.n > DMA_K4_MAX_N) return hipErrorInvalidValue;  // unresolved id
+            const dim3 grid(gemm_tiles(kernel, g.n)), block(512);
+            if (axpi)
+                hipLaunchKernelGGL((gemm_f32_dma_k4_kernel<8, true>), grid, block, 0, s, g);
+            else
+                hipLaunchKernelGGL((gemm_f32_dma_k4_kernel<8, false>), grid, block, 0, s, g);
             return hipGetLastError();
         }
         case MPOW_KERNEL_GEMM_F32_128x64: return launch_variant<128, 64, 2, 2>(g, vec4, axpi, s);

@@ -288,10 +288,12 @@ constexpr int DMA_K4_STAGES = DMA_K4_MAX_N / 128;
 constexpr int DMA_K4_A_STAGE = 32 * 128;       // floats of one stage's X block
 constexpr int DMA_K4_B_STAGE = 128 * 32 + 32 * 8;  // floats of one stage's Y block
 
-// All 256 threads must call it.  As[s] / Bs[s] (s < DMA_K4_STAGES) are LDS
-// arrays of DMA_K4_A_STAGE / DMA_K4_B_STAGE floats.  Same requirements and
-// return value as f32_tile_dma, and n <= DMA_K4_MAX_N.
-template <bool AXPI, typename ExpFn>
+// All KS * 64 threads must call it (KS = 4 or 8 waves: wave w takes the
+// slices w, w + KS, ...).  As[s] / Bs[s] (s < DMA_K4_STAGES) are LDS arrays
+// of DMA_K4_A_STAGE / DMA_K4_B_STAGE floats.  Same requirements and return
+// value as f32_tile_dma, and n <= DMA_K4_MAX_N.  With KS = 8 the products
+// are those of the register-staged 32 x 32 tile with an 8-way K split.
+template <int KS, bool AXPI, typename ExpFn>
 __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
                                                   const float *__restrict__ Y, ExpFn exps,
                                                   float *__restrict__ C, int n, int m0, int n0,
@@ -310,16 +312,18 @@ __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
     const int nst = (n + 127) / 128;  // stages
     const int nsl = (n + 31) / 32;    // 32-wide K slices
 
+    static_assert(KS == 4 || KS == 8, "K split over 4 or 8 waves");
+    constexpr int LPW = 16 / KS;  // loads per wave and stage, of each operand
     // Stage s: X rows m0..m0+31, K [128 s, 128 s + 128) in 16 loads of 2 rows,
-    // Y rows 128 s ... in 16 loads of 8 rows; wave w issues loads 4w .. 4w+3
-    // of each.
+    // Y rows 128 s ... in 16 loads of 8 rows; wave w issues loads LPW w ...
+    // LPW w + LPW - 1 of each.
     auto load_stage = [&](int s) {
         const int k0 = 128 * s;
         float *as = As[s];
         float *bs = Bs[s];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int u = 4 * wave + r;          // rows 2u, 2u + 1
+        for (int r = 0; r < LPW; ++r) {
+            const int u = LPW * wave + r;        // rows 2u, 2u + 1
             const int row = 2 * u + (lane >> 5);
             const int gc = k0 + 4 * ((lane & 31) ^ (row & 15));
             const int gr = m0 + row;
@@ -328,8 +332,8 @@ __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
                                                      0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int g = 4 * wave + r;          // rows 8g .. 8g + 7
+        for (int r = 0; r < LPW; ++r) {
+            const int g = LPW * wave + r;        // rows 8g .. 8g + 7
             const int gr = k0 + 8 * g + (lane >> 3);
             const int gc = n0 + 4 * (lane & 7);
             const unsigned off = (gr < n && gc < n) ? (unsigned)((gr * n + gc) * 4) : OUT;
@@ -351,20 +355,26 @@ __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
     v16f acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    // this wave's slices j = KS u + wave, in ascending order: slice j is the
+    // (j % 4)-th 32-wide part of stage j / 4 (stage 2 u + wave / 4 for KS =
+    // 8, chosen between two fixed arrays so that no pointer is indexed at
+    // run time)
+    const int js = wave & 3;
 #pragma unroll
-    for (int s = 0; s < DMA_K4_STAGES; ++s) {
-        const int j = 4 * s + wave;  // this wave's slice of stage s
+    for (int u = 0; u < DMA_K4_STAGES * 4 / KS; ++u) {
+        const int j = KS * u + wave;
+        const int s = j >> 2;
         if (s < nst && j < nsl) {
-            const float *as = As[s];
-            const float *bs = Bs[s];
+            const float *as = KS == 4 ? As[u] : ((wave >> 2) ? As[2 * u + 1] : As[2 * u]);
+            const float *bs = KS == 4 ? Bs[u] : ((wave >> 2) ? Bs[2 * u + 1] : Bs[2 * u]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int cc = 8 * wave + 4 * h + q;  // chunk of this stage's 128 K
+                const int cc = 8 * js + 4 * h + q;  // chunk of this stage's 128 K
                 f4 a = *(const f4 *)(as + l32 * 128 + 4 * (cc ^ (l32 & 15)));
                 float b[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int k = 32 * wave + 16 * h + 4 * q + t;  // row of the Y block
+                    const int k = 32 * js + 16 * h + 4 * q + t;  // row of the Y block
                     b[t] = bs[k * 32 + 32 * (k >> 4) + l32];
                 }
                 if (!after) {
@@ -379,28 +389,31 @@ __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
         }
     }
 
-    // Every wave parks its partial tile in the first X block; wave w then
-    // finishes rows 8 w + 4 h + i (i < 4) of the tile, register rows 4 w + i:
-    // each element is the four partial tiles added in wave order (the order
-    // of one wave adding the others' into its own), scaled and stored, its
-    // square added to the wave's sum; the waves' sums are then added in
-    // wave order.  Spreading the epilogue over the four waves instead of
-    // leaving it to wave 0 shortens a small product's tail.
-    float *park = As[0];
+    // Every wave parks its partial tile in the first X blocks (wave w in
+    // block w / 4); wave w then finishes register rows (16 / KS) w + i of the
+    // tile: each element is the KS partial tiles added in wave order (the
+    // order of one wave adding the others' into its own), scaled and stored,
+    // its square added to the wave's sum; the waves' sums are then added in
+    // wave order.  Spreading the epilogue over the waves instead of leaving
+    // it to wave 0 shortens a small product's tail.
+    constexpr int RPW = 16 / KS;  // register rows finished per wave
     double *wred = (double *)Bs[0];
     __syncthreads();
+    {
+        float *park = (wave >> 2) ? As[1] : As[0];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) park[(wave * 16 + r) * 64 + lane] = acc[r];
+        for (int r = 0; r < 16; ++r) park[((wave & 3) * 16 + r) * 64 + lane] = acc[r];
+    }
     __syncthreads();
     const PowScale fs = pow2_neg(after ? e.x + e.y : 0);
     double ss = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = 4 * wave + i;
-        float v = park[r * 64 + lane] + park[(16 + r) * 64 + lane];
-        v += park[(32 + r) * 64 + lane];
-        v += park[(48 + r) * 64 + lane];
-        const int row = m0 + 8 * wave + 4 * h + i;
+    for (int i = 0; i < RPW; ++i) {
+        const int r = RPW * wave + i;
+        float v = As[0][r * 64 + lane] + As[0][(16 + r) * 64 + lane];
+#pragma unroll
+        for (int g = 2; g < KS; ++g) v += As[g >> 2][((g & 3) * 16 + r) * 64 + lane];
+        const int row = m0 + 8 * (r >> 2) + 4 * h + (r & 3);
         const int col = n0 + l32;
         if (row < n && col < n) {
             v = v * fs.a * fs.b;
@@ -413,7 +426,11 @@ __device__ __forceinline__ double f32_tile_dma_k4(const float *__restrict__ X,
     if (lane == 0) wred[wave] = ss;
     __syncthreads();
     double t = 0.0;
-    if (tid == 0) t = ((wred[0] + wred[1]) + wred[2]) + wred[3];  // valid in thread 0
+    if (tid == 0) {
+        t = wred[0];
+#pragma unroll
+        for (int w = 1; w < KS; ++w) t += wred[w];  // valid in thread 0
+    }
     __syncthreads();  // the LDS blocks may be reused by the caller
     return t;
 }

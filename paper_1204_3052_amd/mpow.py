@@ -58,7 +58,8 @@ MPOW_KERNEL_GEMM_F32_128_DMA = 16
 MPOW_KERNEL_GEMM_F32_256x128_DMA = 17
 MPOW_KERNEL_GEMM_F32_32_K4_DMA = 18
 MPOW_KERNEL_POWER_WG = 19
-MPOW_KERNEL_COUNT = 20
+MPOW_KERNEL_GEMM_F32_32_K8_DMA = 20
+MPOW_KERNEL_COUNT = 21
 
 # every symbol include/mpow.h declares
 EXPORTS = (

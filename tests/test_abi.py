@@ -198,7 +198,7 @@ def test_fp32_kernel_for_default_choice():
     # (16-byte loads), the register-staged tiles otherwise.
     k = mpow.mpow_fp32_kernel_for
     assert k(0) == -1 and k(-5) == -1
-    assert k(4) == k(300) == k(512) == mpow.MPOW_KERNEL_GEMM_F32_32_K4_DMA
+    assert k(4) == k(300) == k(512) == mpow.MPOW_KERNEL_GEMM_F32_32_K8_DMA
     assert k(1) == k(513) == k(516) == k(767) == mpow.MPOW_KERNEL_GEMM_F32_32_K4
     assert k(300, False) == mpow.MPOW_KERNEL_GEMM_F32_32_K4
     assert k(768) == k(1024) == k(1536) == k(3072) == mpow.MPOW_KERNEL_GEMM_F32_64_DMA

@@ -19,7 +19,7 @@ SAME_ORDER = [mpow.MPOW_KERNEL_GEMM_F32_128, mpow.MPOW_KERNEL_GEMM_F32_64, mpow.
               mpow.MPOW_KERNEL_GEMM_F32_128x64] + DMA
 K_SPLIT = [mpow.MPOW_KERNEL_GEMM_F32_32_K4, mpow.MPOW_KERNEL_GEMM_F32_32_K8,
            mpow.MPOW_KERNEL_GEMM_F32_64_K2, mpow.MPOW_KERNEL_GEMM_F32_128_K2,
-           mpow.MPOW_KERNEL_GEMM_F32_32_K4_DMA]
+           mpow.MPOW_KERNEL_GEMM_F32_32_K4_DMA, mpow.MPOW_KERNEL_GEMM_F32_32_K8_DMA]
 # the LDS-DMA tiles run where n % 4 == 0 (100, 300, 700, 1028), the others
 # fall back to a same-order tile
 SIZES = [1, 33, 100, 257, 300, 513, 700, 1028, 1030]
@@ -72,17 +72,21 @@ def test_dma_tile_operand_scale_paths(fplan, kernel, n):
             assert s1 == s and np.array_equal(M1, M), (n, p, k)
 
 
+@pytest.mark.parametrize("ks", [4, 8])
 @pytest.mark.parametrize("n", [4, 36, 100, 300, 508, 512])
-def test_k4_whole_k_tile_equals_k4(fplan, n):
-    # The 32 x 32 tile with a 4-way K split and the whole K range in LDS adds
-    # in the register-staged K-split tile's order: the same bits, also where
-    # an input's scale sends the first product down the operand-scaled path.
+def test_k4_whole_k_tile_equals_k4(fplan, n, ks):
+    # The 32 x 32 tile with a 4- or 8-way K split and the whole K range in
+    # LDS adds in the register-staged K-split tile's order: the same bits,
+    # also where an input's scale sends the first product down the
+    # operand-scaled path.
+    reg, dma = {4: (mpow.MPOW_KERNEL_GEMM_F32_32_K4, mpow.MPOW_KERNEL_GEMM_F32_32_K4_DMA),
+                8: (mpow.MPOW_KERNEL_GEMM_F32_32_K8, mpow.MPOW_KERNEL_GEMM_F32_32_K8_DMA)}[ks]
     A = inputs.gaussian(n, 1300 + n)
     for p in (2, 17, 100):
         for k in (0, 70, -70):
             Ak = np.ldexp(A, k).astype(np.float32)
-            M0, s0 = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_32_K4, Ak, p)
-            M1, s1 = forced(fplan, mpow.MPOW_KERNEL_GEMM_F32_32_K4_DMA, Ak, p)
+            M0, s0 = forced(fplan, reg, Ak, p)
+            M1, s1 = forced(fplan, dma, Ak, p)
             assert s0 == s1 and np.array_equal(M0, M1), (n, p, k)
             if k == 0:
                 err, tol, _ = check_against_oracle(M1, s1, A, p, seed=n)
