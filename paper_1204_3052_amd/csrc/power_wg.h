@@ -43,9 +43,12 @@
 //    Layouts as the LDS-DMA tiles: X panel chunk c of row r at
 //    c ^ ((r / 2) % 8), Y panel rows with bit 4 of k set swapping their
 //    32-float halves.
-//  - Scaling: operands are always the normalised matrices, so a product's
-//    sums are those of the other kernels with scaled operands (exact powers
-//    of two); s follows s <- 2 (s + eX) for a square and s <- s + eX + eA for
+//  - Scaling: the resident form's operands are always the normalised
+//    matrices; the panel form keeps each product in memory as computed, with
+//    its exponent, and scales the next product's sums by the operands'
+//    exponents, as the product kernels do in their epilogue.  Either way a
+//    product's sums are those of the other kernels (exact powers of two,
+//    wherever nothing is subnormal); s follows s <- 2 (s + eX) for a square and s <- s + eX + eA for
 //    a multiply, and the output is C_G * 2^-e_G with log2 scale s + e_G, or
 //    C_G * 2^s rounded to float32 through float64.
 #pragma once
@@ -549,9 +552,38 @@ __device__ __forceinline__ void panel_product(v16f (&acc)[MB], const int (&bi)[M
     }
 }
 
+// Sum of squares (float64) of all 32 x 32 values of one block of the panel
+// form, in the register order of block_sumsq.  The padding needs no mask: it
+// is exactly zero while every operand value is finite (zero rows and columns
+// of the operands), so adding its squares changes no partial sum; and a
+// non-finite value there comes from a non-finite operand value, which makes
+// the sum over the valid part non-finite as well (exponent 0 either way).
+__device__ __forceinline__ double block_sumsq_all(const v16f &acc) {
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ss += (double)acc[r] * (double)acc[r];
+    return ss;
+}
+
+// The stored running matrix's exponent may stay in memory (the raw product
+// is written back, its power-of-two scale applied to the next product's
+// sums) while the next product's combined operand exponent is at least this
+// low: the range the product kernels also scale in their epilogue.
+constexpr int kPanelRawMinExp = -16;
+
 // The power's products for a wave with CNT blocks, block rows r0 .. r0 +
 // CNT - 1 of block column c0 (CNT fixed, so the K loop is fully unrolled
 // over the blocks); see wg_power_panel.
+//
+// The running matrix in memory is N * 2^t, N the normalised matrix (norm in
+// [1, 2)) and t its stored exponent.  A product of stored operands with
+// exponents tl and tr gives the sums of the normalised product times
+// 2^(tl + tr), exactly (power-of-two scaling commutes with every rounding
+// while nothing is subnormal); they are scaled by 2^-(tl + tr) before use.
+// The result C (norm below 4) is written back as it is, t = e(C), before its
+// exponent is known, so the stores drain while the waves sum its squares,
+// and one barrier covers both.  Only where e(C) < kPanelRawMinExp (a
+// product far below norm 1) is it rewritten as C * 2^-e with t = 0.
 template <int NPMAX, int NW, int CNT, int MB>
 __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t p, float *out,
                                                  double *scale, float *SX, float *SAm, float *L0,
@@ -562,47 +594,69 @@ __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t 
     int bi[MB];
 #pragma unroll
     for (int j = 0; j < MB; ++j) bi[j] = r0 + j;
-    auto bcol = [&](int) { return c0; };
 
     const int top = 63 - __clzll((unsigned long long)p);
     int eX = eA;
+    int tX = 0;  // stored exponent of the running matrix in SX
     double s = 0.0, S = 0.0;
     bool first = true;
     v16f acc[MB];
+    const __amdgpu_buffer_rsrc_t rS =
+        __builtin_amdgcn_make_buffer_rsrc((void *)SX, (short)0, npad * npad * 4, 0x00020000);
+    // stores C * f of the wave's blocks into SX: buffer stores with one
+    // offset register per block and the row offsets in scalar registers
+    auto store_blocks = [&](float fa, float fb) {
+#pragma unroll
+        for (int j = 0; j < CNT; ++j) {
+            const int vo = ((bi[j] * 32 + 4 * h) * npad + c0 * 32 + l32) * 4;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int so = (8 * (r >> 2) + (r & 3)) * npad * 4;
+                __builtin_amdgcn_raw_buffer_store_b32(
+                    __builtin_bit_cast(unsigned, acc[j][r] * fa * fb), rS, vo, so, 0);
+            }
+        }
+    };
     for (int bit = top - 1; bit >= 0; --bit) {
         for (int pass = 0; pass < 2; ++pass) {
             const bool mul = pass == 1;
             if (mul && !((p >> bit) & 1)) break;
             const bool last = bit == 0 && (mul || !(p & 1));
             const float *left = first ? SAm : SX;
+            const int tl = first ? 0 : tX, tr = mul ? 0 : tl;
             panel_product<NPMAX, NW, CNT, MB>(acc, bi, c0, npad, left, mul ? SAm : left, L0, L1,
                                               wave);
             first = false;
+            // (ends with a barrier: SX is no longer read)
+            if (tl + tr != 0) {
+                const PowScale fs = pow2_neg(tl + tr);
+#pragma unroll
+                for (int j = 0; j < CNT; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[j][r] = acc[j][r] * fs.a * fs.b;
+            }
+            if (!last) store_blocks(1.0f, 1.0f);
             double ss = 0.0;
 #pragma unroll
-            for (int j = 0; j < CNT; ++j) ss += block_sumsq(acc[j], bi[j], bcol(j), n);
-            S = wg_sum<NW>(ss, red);
+            for (int j = 0; j < CNT; ++j) ss += block_sumsq_all(acc[j]);
+            ss = wave_sum_lane0(ss);
+            if (lane == 0) red[wave] = ss;
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // the write-back is done
+            __syncthreads();
+            S = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) S += red[w];
             s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
             eX = exponent_of_sumsq(S);
             if (last) break;
-            // C * 2^-e over the running matrix (its padding stays zero):
-            // buffer stores with one offset register per block and the row
-            // offsets in scalar registers
-            const PowScale f = pow2_neg(eX);
-            const __amdgpu_buffer_rsrc_t rS =
-                __builtin_amdgcn_make_buffer_rsrc((void *)SX, (short)0, npad * npad * 4, 0x00020000);
-#pragma unroll
-            for (int j = 0; j < CNT; ++j) {
-                const int vo = ((bi[j] * 32 + 4 * h) * npad + bcol(j) * 32 + l32) * 4;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int so = (8 * (r >> 2) + (r & 3)) * npad * 4;
-                    __builtin_amdgcn_raw_buffer_store_b32(
-                        __builtin_bit_cast(unsigned, acc[j][r] * f.a * f.b), rS, vo, so, 0);
-                }
+            tX = eX;
+            if (eX < kPanelRawMinExp) {
+                const PowScale f = pow2_neg(eX);
+                store_blocks(f.a, f.b);
+                __builtin_amdgcn_s_waitcnt(0x0f70);
+                __syncthreads();
+                tX = 0;
             }
-            __builtin_amdgcn_s_waitcnt(0x0f70);  // stores done before the next product reads
-            __syncthreads();
         }
     }
     double sc = s;
@@ -610,7 +664,7 @@ __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t 
     const PowScale f = pow2_neg(eX);
 #pragma unroll
     for (int j = 0; j < CNT; ++j)
-        block_write_out(acc[j], bi[j], bcol(j), n, out, scale != nullptr, f, (int)sc);
+        block_write_out(acc[j], bi[j], c0, n, out, scale != nullptr, f, (int)sc);
     if (scale && threadIdx.x == 0) *scale = (S == 0.0) ? 0.0 : s + (double)eX;
 }
 

@@ -331,6 +331,41 @@ def test_whole_power_instance_equals_plain_bitwise(plans, shape):
         mpow.mpow_plan_tile_table(hb, saved)
 
 
+def test_panel_products_far_below_norm_one(plans):
+    # Nearly nilpotent inputs A = J + 2^k G (J a single corner entry, so
+    # J^2 = 0): the first product's norm is about 2^k times that of the
+    # normalised input.  The streamed-panel form keeps a product in memory as
+    # computed down to exponent -16 (k = -6) and stores it rescaled below
+    # that (k = -20, -40); either way every result keeps the plain path's
+    # bits and meets the oracle's bar.
+    hb, hp = plans
+    saved = mpow.mpow_plan_tile_table(hb)
+    mpow.mpow_plan_tile_table(hb, [4] * mpow.TILE_TABLE_LEN)
+    try:
+        mats, ps = [], []
+        for i, n in enumerate((16, 40, 64, 100, 128, 160, 200, 256)):
+            for j, k in enumerate((-6, -20, -40)):
+                A = np.ldexp(inputs.gaussian(n, 9100 + 10 * i + j).astype(np.float64), k)
+                A[0, n - 1] += 1.0
+                A = A.astype(np.float32)
+                for p in (2, 3, 5, 17, 100):
+                    mats.append(A)
+                    ps.append(p)
+        pk = Packed(mats)
+        run_batch(hb, pk, ps)
+        for i, (A, p) in enumerate(zip(mats, ps)):
+            Mb, sb = pk.result(i)
+            Mp, sp = run_gpu(hp, A, p)
+            assert np.array_equal(Mb, Mp) and sb == sp, (A.shape[0], p, i)
+            if i % 4 == 0:
+                ref = oracle.mpow_binary(A, p)
+                err = oracle.rel_err(Mb, sb, *ref)
+                floor = oracle.floor_estimate(A, p, inputs.relative_signs(A.shape[0], i), ref=ref)
+                assert err <= tol_fp32(floor), (A.shape[0], p, err)
+    finally:
+        mpow.mpow_plan_tile_table(hb, saved)
+
+
 def test_back_to_back_batches_with_launch_groups(plans):
     # Several batches in flight on one stream (no synchronisation between the
     # calls, so descriptor slots and workers' scratch are reused while earlier
