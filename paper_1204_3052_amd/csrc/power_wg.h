@@ -262,24 +262,37 @@ __device__ __forceinline__ void res_product(v16f (&acc)[MB], int nb, int wave, c
         bi[j] = t / nb;
         bj[j] = t - bi[j] * nb;
     }
+    // operands of K step (kt, q); the reads of the next step are issued
+    // before the MFMAs of the current one, so their LDS latency is hidden
+    struct Ops {
+        f4 a[MB];
+        float b[MB][4];
+    };
+    auto read = [&](Ops &o, int kt, int q) {
+#pragma unroll
+        for (int j = 0; j < CNT; ++j) {
+            const int row = bi[j] * 32 + l32;
+            o.a[j] = *(const f4 *)(left + row * LD + 4 * ((8 * kt + 4 * h + q) ^ res_swz(row)));
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                o.b[j][t] = right[res_idx<LD>(32 * kt + 16 * h + 4 * q + t, bj[j] * 32 + l32)];
+        }
+    };
+    Ops ops[2];
+    read(ops[0], 0, 0);
     for (int kt = 0; kt < nb; ++kt) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            f4 a[MB];
-            float bv[MB][4];
-#pragma unroll
-            for (int j = 0; j < CNT; ++j) {
-                const int row = bi[j] * 32 + l32;
-                a[j] = *(const f4 *)(left + row * LD + 4 * ((8 * kt + 4 * h + q) ^ res_swz(row)));
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    bv[j][t] = right[res_idx<LD>(32 * kt + 16 * h + 4 * q + t, bj[j] * 32 + l32)];
-            }
+            if (q < 3)
+                read(ops[(q + 1) & 1], kt, q + 1);
+            else if (kt + 1 < nb)
+                read(ops[0], kt + 1, 0);
+            const Ops &o = ops[q & 1];
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int j = 0; j < CNT; ++j)
-                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j][t], bv[j][t], acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a[j][t], o.b[j][t], acc[j], 0, 0, 0);
         }
     }
 }
@@ -318,14 +331,17 @@ __device__ __forceinline__ void res_power_body(int n, int64_t p, float *out, dou
             s = mul ? s + (double)eX + (double)eA : 2.0 * (s + (double)eX);
             eX = exponent_of_sumsq(S);
             if (last) break;
-            // C * 2^-e over the running matrix (its padding stays zero)
+            // C * 2^-e over the running matrix; its padding is written as
+            // zeros (a non-finite operand value makes the padding of C NaN,
+            // 0 * inf, which must not reach the next product's sums)
             const PowScale f = pow2_neg(eX);
 #pragma unroll
             for (int j = 0; j < CNT; ++j) {
+                const int col = bj[j] * 32 + l32;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int row = bi[j] * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                    LX[res_idx<LD>(row, bj[j] * 32 + l32)] = acc[j][r] * f.a * f.b;
+                    LX[res_idx<LD>(row, col)] = (row < n && col < n) ? acc[j][r] * f.a * f.b : 0.0f;
                 }
             }
             __syncthreads();
@@ -554,8 +570,8 @@ __device__ __forceinline__ void panel_product(v16f (&acc)[MB], const int (&bi)[M
 
 // Sum of squares (float64) of all 32 x 32 values of one block of the panel
 // form, in the register order of block_sumsq.  The padding needs no mask: it
-// is exactly zero while every operand value is finite (zero rows and columns
-// of the operands), so adding its squares changes no partial sum; and a
+// is exactly zero while every operand value is finite (the operands' padding
+// is stored as zeros), so adding its squares changes no partial sum; and a
 // non-finite value there comes from a non-finite operand value, which makes
 // the sum over the valid part non-finite as well (exponent 0 either way).
 __device__ __forceinline__ double block_sumsq_all(const v16f &acc) {
@@ -617,6 +633,19 @@ __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t 
             }
         }
     };
+    // zeros over the padding of the wave's blocks on the matrix's edge: a
+    // non-finite operand value makes it NaN (0 * inf), which must not reach
+    // the next product's sums (elsewhere it is exactly zero already)
+    auto zero_padding = [&]() {
+#pragma unroll
+        for (int j = 0; j < CNT; ++j) {
+            if ((bi[j] + 1) * 32 <= n && (c0 + 1) * 32 <= n) continue;
+            const int lim = c0 * 32 + l32 < n ? n - bi[j] * 32 - 4 * h : 0;  // rows below lim are valid
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (8 * (r >> 2) + (r & 3) >= lim) acc[j][r] = 0.0f;
+        }
+    };
     for (int bit = top - 1; bit >= 0; --bit) {
         for (int pass = 0; pass < 2; ++pass) {
             const bool mul = pass == 1;
@@ -635,7 +664,10 @@ __device__ __forceinline__ void panel_power_body(const float *A, int n, int64_t 
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[j][r] = acc[j][r] * fs.a * fs.b;
             }
-            if (!last) store_blocks(1.0f, 1.0f);
+            if (!last) {
+                zero_padding();
+                store_blocks(1.0f, 1.0f);
+            }
             double ss = 0.0;
 #pragma unroll
             for (int j = 0; j < CNT; ++j) ss += block_sumsq_all(acc[j]);

@@ -366,6 +366,35 @@ def test_panel_products_far_below_norm_one(plans):
         mpow.mpow_plan_tile_table(hb, saved)
 
 
+@pytest.mark.parametrize("shape", [3, 4])
+def test_whole_power_non_finite_inputs_match_plain(plans, shape):
+    # A NaN or an infinity in the input spreads through the products; the
+    # whole-power forms (whose sums of squares include the zero padding
+    # unmasked in the panel form) give the plain path's values, NaNs in the
+    # same places, and the same log2 scale.
+    hb, hp = plans
+    saved = mpow.mpow_plan_tile_table(hb)
+    mpow.mpow_plan_tile_table(hb, [shape] * mpow.TILE_TABLE_LEN)
+    try:
+        mats, ps = [], []
+        for i, n in enumerate((5, 40, 100, 144, 200, 256)):
+            for j, bad in enumerate((np.nan, np.inf, -np.inf)):
+                A = inputs.gaussian(n, 9300 + 10 * i + j)
+                A[(3 * j) % n, (7 + j) % n] = bad
+                for p in (2, 3, 17):
+                    mats.append(A)
+                    ps.append(p)
+        pk = Packed(mats)
+        run_batch(hb, pk, ps)
+        for i, (A, p) in enumerate(zip(mats, ps)):
+            Mb, sb = pk.result(i)
+            Mp, sp = run_gpu(hp, A, p)
+            assert np.array_equal(Mb, Mp, equal_nan=True) and sb == sp, (A.shape[0], p, i)
+            assert not np.all(np.isfinite(Mb)), (A.shape[0], p)
+    finally:
+        mpow.mpow_plan_tile_table(hb, saved)
+
+
 def test_back_to_back_batches_with_launch_groups(plans):
     # Several batches in flight on one stream (no synchronisation between the
     # calls, so descriptor slots and workers' scratch are reused while earlier
