@@ -366,12 +366,12 @@ def test_panel_products_far_below_norm_one(plans):
         mpow.mpow_plan_tile_table(hb, saved)
 
 
-@pytest.mark.parametrize("shape", [3, 4])
-def test_whole_power_non_finite_inputs_match_plain(plans, shape):
-    # A NaN or an infinity in the input spreads through the products; the
-    # whole-power forms (whose sums of squares include the zero padding
-    # unmasked in the panel form) give the plain path's values, NaNs in the
-    # same places, and the same log2 scale.
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+def test_non_finite_inputs_match_plain(plans, shape):
+    # A NaN or an infinity in the input spreads through the products; every
+    # tile shape (the whole-power forms keep zero padding in their running
+    # matrix, and the panel form sums it unmasked) gives the plain path's
+    # values, NaNs in the same places, and the same log2 scale.
     hb, hp = plans
     saved = mpow.mpow_plan_tile_table(hb)
     mpow.mpow_plan_tile_table(hb, [shape] * mpow.TILE_TABLE_LEN)
