@@ -46,6 +46,21 @@ def test_power_wg_equals_same_order_tiles(wplans, n):
         assert err <= tol, (n, p, err, tol)
 
 
+@pytest.mark.parametrize("n", [5, 40, 64, 100, 128])
+def test_power_wg_non_finite_inputs_match_tiles(wplans, n):
+    # NaN and +-inf inputs: the running matrix's padding is kept zero, so
+    # the values (NaNs in the same places) and the log2 scale are the
+    # tiles'.
+    hw, hs = wplans
+    for j, bad in enumerate((np.nan, np.inf, -np.inf)):
+        A = inputs.gaussian(n, 940 + 3 * n + j)
+        A[(3 * j) % n, (7 + j) % n] = bad
+        for p in (2, 3, 17):
+            Mw, sw = run_gpu(hw, A, p)
+            Ms, ss = run_gpu(hs, A, p)
+            assert np.array_equal(Mw, Ms, equal_nan=True) and sw == ss, (n, p, j)
+
+
 def test_power_wg_scaled_inputs_and_alias(wplans):
     hw, hs = wplans
     for k in (70, -70, 120):
