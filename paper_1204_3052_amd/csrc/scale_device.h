@@ -56,11 +56,41 @@ __device__ __forceinline__ double block_sum_partials(const double *__restrict__ 
     return S;
 }
 
+namespace detail {
+// Value of lane l + 32 (lanes 0 .. 31; v_permlane32_swap), of lane l ^ 16
+// (ds_swizzle, xor mode) and of lane l + N within the lane's row of 16
+// (DPP row_shl; lanes past the row's end read 0), for a double as two
+// 32-bit halves.  Every lane of the wave must be active.
+__device__ __forceinline__ double lane_plus32(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_permlane32_swap(hi, hi, false, false)[1],
+                            __builtin_amdgcn_permlane32_swap(lo, lo, false, false)[1]);
+}
+__device__ __forceinline__ double lane_xor16(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_ds_swizzle(hi, 0x401F),
+                            __builtin_amdgcn_ds_swizzle(lo, 0x401F));
+}
+template <int N>
+__device__ __forceinline__ double lane_row_plus(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0x100 + N, 0xf, 0xf, true),
+                            __builtin_amdgcn_update_dpp(0, lo, 0x100 + N, 0xf, 0xf, true));
+}
+}  // namespace detail
+
 // Fixed-order reduction of one double per lane across a 64-lane wave; the
-// result is valid in lane 0.
+// result is valid in lane 0: the tree v_l += v_(l + d) for d = 32, 16, ...,
+// 1, the additions of __shfl_down's tree, by register-to-register lane
+// moves (permlane, swizzle and DPP) instead of LDS permutes, whose latency
+// each of the six steps waited out.  Every lane of the wave must be active.
 __device__ __forceinline__ double wave_sum_lane0(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    v += detail::lane_plus32(v);
+    v += detail::lane_xor16(v);
+    v += detail::lane_row_plus<8>(v);
+    v += detail::lane_row_plus<4>(v);
+    v += detail::lane_row_plus<2>(v);
+    v += detail::lane_row_plus<1>(v);
     return v;
 }
 
