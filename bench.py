@@ -62,6 +62,89 @@ def host_cores() -> int:
     return len(os.sched_getaffinity(0))
 
 
+class ClockSampler:
+    """Samples the GPU's graphics clock (MHz) through the amdsmi module every
+    `period` seconds on a background thread while the `with` block runs, so
+    that a rate can be read against the clock it ran at (MI355X's peaks
+    assume 2.4 GHz).  Reports None, with the reason, where amdsmi is missing,
+    does not answer, or sees more than one GPU."""
+
+    def __init__(self, period: float = 0.1, delay: float = 0.0):
+        self.period = period
+        self.delay = delay
+        self.samples = []
+        self.error = None
+        self._thread = None
+        self._stop = None
+
+    def _read(self):
+        try:
+            info = self._smi.amdsmi_get_clock_info(self._h, self._smi.AmdSmiClkType.GFX)
+            v = info.get("clk") if isinstance(info, dict) else None
+            if isinstance(v, (int, float)) and v > 0:
+                return float(v)
+        except Exception:
+            pass
+        m = self._smi.amdsmi_get_gpu_metrics_info(self._h)
+        for key in ("current_gfxclks", "current_gfxclk", "average_gfxclk_frequency"):
+            v = m.get(key)
+            if isinstance(v, (list, tuple)):
+                v = [x for x in v if isinstance(x, (int, float)) and 0 < x < 65535]
+                if v:
+                    return float(sum(v)) / len(v)
+            elif isinstance(v, (int, float)) and 0 < v < 65535:
+                return float(v)
+        raise RuntimeError("no graphics clock in the amdsmi answers")
+
+    def __enter__(self):
+        try:
+            import threading
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            handles = amdsmi.amdsmi_get_processor_handles()
+            if len(handles) != 1:
+                raise RuntimeError(f"{len(handles)} GPUs visible to amdsmi")
+            self._h = handles[0]
+            self._read()
+            self._stop = threading.Event()
+
+            def loop():
+                if self._stop.wait(self.delay):
+                    return
+                while not self._stop.is_set():
+                    try:
+                        self.samples.append(self._read())
+                    except Exception as e:  # keep the samples taken so far
+                        self.error = str(e)[:120]
+                        return
+                    self._stop.wait(self.period)
+
+            self._thread = threading.Thread(target=loop, daemon=True)
+            self._thread.start()
+        except Exception as e:
+            self.error = f"{type(e).__name__}: {str(e)[:120]}"
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread is not None:
+            self._stop.set()
+            self._thread.join(timeout=5)
+        try:
+            if self._thread is not None or self.error is None:
+                self._smi.amdsmi_shut_down()
+        except Exception:
+            pass
+        return False
+
+    def summary(self):
+        if not self.samples:
+            return {"source": "amdsmi", "samples": 0, "error": self.error}
+        v = sorted(self.samples)
+        return {"source": "amdsmi", "samples": len(v), "median": round(v[len(v) // 2]),
+                "min": round(v[0]), "max": round(v[-1])}
+
+
 def warm_up(fn, calls: int, dev, seconds: float) -> int:
     """Runs fn at least `calls` times and for at least `seconds` of wall
     time, then waits for the device.  A GPU that was idle or lightly loaded
@@ -1000,6 +1083,14 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize(dev)
+    # the graphics clock while the same steps run, sampled over a second of
+    # untimed steps (the queries stay out of the timed region; the first
+    # quarter second is skipped, the clock reading lagging behind the load)
+    with ClockSampler(0.1, delay=0.25) as clock:
+        t_clk = time.perf_counter()
+        while time.perf_counter() - t_clk < 1.0:
+            step()
+            torch.cuda.synchronize(dev)
 
     # per-case timing outside the timed region (context only); the results of
     # the sizes the oracle leg can reach are kept for its error check
@@ -1076,6 +1167,7 @@ def main():
                    "sizes": list(SIZES), "powers": list(POWERS), "parallelism": "single GPU"},
         "pct_fp32_mfma_peak": round(value / (FP32_MFMA_PEAK_TFLOPS * 1e3) * 100, 2),
         "roofline": roofline,
+        "gfx_clock_mhz": clock.summary(),
         "per_case": per_case,
     }
     lat, lat_kept = stochastic_latency(dev, stream)
