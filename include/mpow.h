@@ -256,7 +256,9 @@ mpow_status mpow_run_batched(mpow_plan_t plan, int count, const float *const *A,
  * n = 64, eight waves and 128 KB above) and streams K panels of both from
  * scratch for n > 128; 4 always streams K panels (64 KB of LDS, two
  * workgroups per CU, up to n = 128; 128 KB above).  Every shape gives
- * bit-identical results; only speed differs.  A batch runs as one launch
+ * bit-identical results wherever no intermediate value is subnormal (the
+ * shapes apply the same power-of-two scales at different points of a
+ * product); only speed differs.  A batch runs as one launch
  * per group of matrices that share a kernel instance (at most five, in
  * order on the stream): the tiled shapes on the smallest instance that
  * holds every tiled shape used (without shape 0 or 2: a 64x64-only instance
