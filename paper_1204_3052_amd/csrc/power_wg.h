@@ -581,10 +581,10 @@ __device__ __forceinline__ double block_sumsq_all(const v16f &acc) {
     return ss;
 }
 
-// The stored running matrix's exponent may stay in memory (the raw product
-// is written back, its power-of-two scale applied to the next product's
-// sums) while the next product's combined operand exponent is at least this
-// low: the range the product kernels also scale in their epilogue.
+// A product stays in memory as computed (its power-of-two scale applied to
+// the next product's sums) while its exponent is at least this, so that the
+// next product's two operand exponents add up to at least -32: the range in
+// which the product kernels also scale in their epilogue.
 constexpr int kPanelRawMinExp = -16;
 
 // The power's products for a wave with CNT blocks, block rows r0 .. r0 +
