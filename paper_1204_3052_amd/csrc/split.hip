@@ -202,10 +202,13 @@ __device__ __forceinline__ void split_epilogue(const v16f (&acc)[FM][FN], const 
     const bool fused = ex.x + ex.y != 0;
     const PowScale f = pow2_neg(ex.x + ex.y);
     double ss = 0.0;
+    typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int j = 0; j < FN; ++j) {
+            // transposed parts of rows 8 rb + 4 grp .. + 3 of column col
+            u16x4 wt[PARTS ? NP : 1][4];
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
                 const int row0 = m0w + i * 32 + 8 * rb + 4 * grp;
@@ -234,12 +237,8 @@ __device__ __forceinline__ void split_epilogue(const v16f (&acc)[FM][FN], const 
                         T *rm = (T *)g.prm[k];
 #pragma unroll
                         for (int t = 0; t < 4; ++t) rm[(int64_t)(row0 + t) * ld + col] = pv[k][t];
-                        // four consecutive rows of column col: one 8-byte store
-                        typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-                        u16x4 w;
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) w[t] = __builtin_bit_cast(unsigned short, pv[k][t]);
-                        *(u16x4 *)((T *)g.ptr[k] + (int64_t)col * ld + row0) = w;
+                        for (int t = 0; t < 4; ++t) wt[k][rb][t] = __builtin_bit_cast(unsigned short, pv[k][t]);
                     }
                 } else {
 #pragma unroll
@@ -247,6 +246,36 @@ __device__ __forceinline__ void split_epilogue(const v16f (&acc)[FM][FN], const 
                         if (row0 + t < n && col < n) g.C[(int64_t)(row0 + t) * n + col] = v[t];
                 }
             }
+            if constexpr (PARTS) {
+                // Transposed parts, eight consecutive rows of column col per
+                // 16-byte store: for the row groups rb and rb + 1, the lane of
+                // half 0 (rows 8 rb + 0 .. 3) takes rows 8 rb + 4 .. 7 from its
+                // partner in half 1, which takes rows 8 rb + 8 .. 11 in turn
+                // (v_permlane32_swap: [1] reads the upper half's lane, [0] the
+                // lower half's).
+                const int col = n0w + j * 32 + l32;
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+#pragma unroll
+                    for (int rb = 0; rb < 4; rb += 2) {
+                        typedef int i32x2 __attribute__((ext_vector_type(2)));
+                        const i32x2 a = __builtin_bit_cast(i32x2, wt[k][rb]);
+                        const i32x2 b = __builtin_bit_cast(i32x2, wt[k][rb + 1]);
+                        // every lane takes part in the lane moves
+                        i32x2 sa, sb;
+                        sa[0] = __builtin_amdgcn_permlane32_swap(a[0], a[0], false, false)[1];
+                        sa[1] = __builtin_amdgcn_permlane32_swap(a[1], a[1], false, false)[1];
+                        sb[0] = __builtin_amdgcn_permlane32_swap(b[0], b[0], false, false)[0];
+                        sb[1] = __builtin_amdgcn_permlane32_swap(b[1], b[1], false, false)[0];
+                        const i32x2 mine = grp == 0 ? a : b, other = grp == 0 ? sa : sb;
+                        typedef int i32x4 __attribute__((ext_vector_type(4)));
+                        const i32x4 w = grp == 0 ? i32x4{mine[0], mine[1], other[0], other[1]}
+                                                 : i32x4{other[0], other[1], mine[0], mine[1]};
+                        const int r8 = m0w + i * 32 + 8 * rb + 8 * grp;
+                        *(i32x4 *)((T *)g.ptr[k] + (int64_t)col * ld + r8) = w;
+                    }
+            }
+        }
     ss = wave_sum_lane0(ss);
     if (lane == 0) red[wave] = ss;
     __syncthreads();
