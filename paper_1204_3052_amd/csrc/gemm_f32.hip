@@ -17,6 +17,39 @@ namespace {
 // LDS scratch of NT doubles; contains barriers.
 template <int NT>
 __device__ __forceinline__ OperandExps operand_exponents(const GemmLaunch &g, double *red) {
+    if (g.normA) {
+        // the input's own sum of squares: thread t adds 16-byte chunks t,
+        // t + NT, ... in turn, then the waves' trees and the waves in order
+        const f4 *M4 = (const f4 *)g.normA;
+        const int t4 = g.n * g.n / 4;
+        double acc = 0.0;
+        constexpr int U = 8;
+        for (int b = threadIdx.x; b < t4; b += NT * U) {
+            f4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = b + u * NT;
+                v[u] = i < t4 ? M4[i] : f4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc += (double)v[u][c] * (double)v[u][c];
+        }
+        acc = wave_sum_lane0(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        double S = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) S += red[w];
+        __syncthreads();  // `red` may be written again
+        const int e = exponent_of_sumsq(S);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (g.eSlot) *g.eSlot = e;
+            if (g.eSlotY) *g.eSlotY = e;
+        }
+        return OperandExps{e, e};
+    }
     const int eX =
         g.partX ? exponent_of_sumsq(sum_partials<NT>(g.partX, g.nPartX, red)) : g.eXfix;
     int eY = eX;

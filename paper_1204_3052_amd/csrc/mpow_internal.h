@@ -165,7 +165,17 @@ struct GemmLaunch {
     // stream) instead of being reduced from partY
     const int *eYin = nullptr;
     float alpha = 1.0f;      // the identity-adding epilogue: C = alpha X'Y' + I
+    // non-null (X = Y = normA, n % 4 == 0, 16-byte aligned; the whole-K
+    // 32 x 32 kernels only): each workgroup sums normA's squares itself, in
+    // one fixed order, for eX = eY, instead of reducing partials of a
+    // separate launch
+    const float *normA = nullptr;
 };
+
+// Largest n for which the first product of a float32 power reduces the
+// input's norm itself (GemmLaunch::normA): every workgroup reads the whole
+// input once more, n^2 floats.
+constexpr int kNormInKernelMaxN = 256;
 
 // Split of a float32 matrix into 16-bit hi/lo, row-major and transposed,
 // zero-padded to ld x ld.

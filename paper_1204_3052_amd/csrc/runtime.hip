@@ -221,22 +221,35 @@ int schedule_of(int64_t p, uint8_t *ops) {
 // partial sums again (one device load instead of a workgroup-wide reduction
 // of hundreds of partials, whose latency every workgroup of a small product
 // pays).
+//
+// For small n on the whole-K 32 x 32 kernels the first product reduces the
+// input's norm itself (every workgroup reads the n^2 inputs once more), so
+// the power needs no separate norm launch before it: a dependent launch
+// costs a few microseconds, about what a whole small product takes.
+static bool fp32_norm_in_kernel(const Workspace &ws, const float *A, int n) {
+    const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
+    const int kernel = gemm_resolve(ws_product_kernel(ws, n, vec4), n, vec4);
+    return vec4 && n <= kNormInKernelMaxN &&
+           (kernel == MPOW_KERNEL_GEMM_F32_32_K4_DMA || kernel == MPOW_KERNEL_GEMM_F32_32_K8_DMA);
+}
+
 hipError_t run_fp32(const Workspace &ws, const float *A, int n, int64_t p, const uint8_t *ops,
-                    int G, int nbA, float *out, double *log2_scale, hipStream_t s,
-                    TimingSink *timing) {
+                    int G, int nbA, bool normInKernel, float *out, double *log2_scale,
+                    hipStream_t s, TimingSink *timing) {
     const bool vec4 = (n % 4 == 0) && (((uintptr_t)A & 15) == 0);
     int kernel = ws_product_kernel(ws, n, vec4);
     kernel = gemm_resolve(kernel, n, vec4);
     const int tiles = gemm_tiles(kernel, n);
     const double flop = 2.0 * (double)n * (double)n * (double)n;
     const float *X = A;
-    const double *partX = ws.partA;
-    int nPartX = nbA;
+    const double *partX = normInKernel ? nullptr : ws.partA;
+    int nPartX = normInKernel ? 0 : nbA;
     for (int k = 1; k <= G; ++k) {
         GemmLaunch g;
         g.X = X;
         g.partX = partX;
         g.nPartX = nPartX;
+        if (k == 1 && normInKernel) g.normA = A;  // A^2: both operands are A
         if (ops[k - 1] == 0) {
             g.Y = X;
             g.partY = partX;
@@ -444,9 +457,11 @@ hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, 
         return hipSuccess;
     }
     const int nbA = norm_blocks(n);
-    MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
     uint8_t ops[MPOW_MAX_STEPS];
     const int G = schedule_of(p, ops);
+    const bool normInKernel =
+        ws.mode == MPOW_FP32 && bw == 1 && G > 0 && fp32_norm_in_kernel(ws, A, n);
+    if (!normInKernel) MPOW_TRY(launch_sumsq(A, n, ws.partA, nbA, s));
     if (G == 0) return launch_finish(A, n, ws.partA, nbA, ws.escale, p, out, log2_scale, s);
     if (ws.mode != MPOW_FP32) return run_split(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
     if (bw > 1) {
@@ -455,7 +470,7 @@ hipError_t enqueue_power(const Workspace &ws, const float *A, int n, int64_t p, 
         const int gw = window_schedule(p, bw, wops, kMaxGraphOps, &result);
         if (gw > 0) return run_fp32_window(ws, A, n, wops, gw, result, nbA, out, log2_scale, s, timing);
     }
-    return run_fp32(ws, A, n, p, ops, G, nbA, out, log2_scale, s, timing);
+    return run_fp32(ws, A, n, p, ops, G, nbA, normInKernel, out, log2_scale, s, timing);
 }
 
 hipError_t enqueue_power_naive(const Workspace &ws, const float *A, int n, int64_t p, float *out,
